@@ -1,0 +1,174 @@
+"""Benchmark: batched moment propagation with adsorption/desorption on one MI355X.
+
+Workload (batched species and geometries): four slit pores of width
+W = 16, 32, 48, 64 fluid layers with a 64 x 64 lateral extent (64 x 64 x (W+2)
+lattices), each carrying 64 species with (k_a, k_d) drawn log-uniform in
+[1e-4, 1e-1] from fixed seeds, D_b = 1e-2, in a Poiseuille flow at Peclet 10
+(Pe = W vbar / D_b) from the BGK solver; FP32 propagation with FP64 sums.
+One step advances all 256 (geometry, species) pairs by one time step, all
+four propagated quantities and their adsorbed counterparts, and records the
+VACF and conserved totals.
+
+Prints one JSON line. ``value`` is fluid-node-species updates per second over
+the timed steps (inputs resident on the GPU). ``roofline`` prices the
+propagation kernel against the MI355X HBM peak; ``cpu_baseline`` times the
+FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WIDTHS = (16, 32, 48, 64)
+NXY = 64
+N_SPECIES = 64
+D_B = 0.01
+PECLET = 10.0
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(lb, inputs):
+    flows, species, nf, ni = [], [], [], []
+    for i, W in enumerate(WIDTHS):
+        mask = inputs.slit_mask(NXY, NXY, W + 2)
+        g = inputs.poiseuille_force(PECLET, D_B, W)
+        t0 = time.time()
+        fl = lb.lb_flow_solve(mask, 1.0, [g, 0.0, 0.0], 1e-10, 400000)
+        log(f"flow W={W}: {fl.steps} BGK steps, residual {fl.residual:.2e}, {time.time() - t0:.2f}s")
+        ka, kd = inputs.loguniform_rates(N_SPECIES, 1e-4, 1e-1, seed=1000 + W)
+        flows.append(fl)
+        species.append({"D_b": D_B, "k_a": ka, "k_d": kd})
+        _, f, n = fl.classes()
+        nf.append(f)
+        ni.append(n)
+    return flows, species, nf, ni
+
+
+def traffic_record():
+    """Measured HBM bytes per launch of the propagation kernel, if taken on the
+    current kernel source (profiles/mp_step_traffic.json)."""
+    path = os.path.join(ROOT, "profiles", "mp_step_traffic.json")
+    src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(inputs, steps: int):
+    """FP64 oracle on the widest slit of the workload, one species, `steps` steps."""
+    import oracle
+    oracle.build()
+    W = WIDTHS[-1]
+    mask = inputs.slit_mask(NXY, NXY, W + 2)
+    ka, kd = inputs.loguniform_rates(N_SPECIES, 1e-4, 1e-1, seed=1000 + W)
+    g = inputs.poiseuille_force(PECLET, D_B, W)
+    # the flow is set up outside the timed part, as on the GPU
+    col = oracle.bgk(inputs.slit_mask(1, 1, W + 2), 1.0, [g, 0, 0], 1e-10, 400000)
+    u = np.broadcast_to(col["u"], (3, W + 2, NXY, NXY)).copy()
+    t0 = time.time()
+    oracle.vacf(mask, u, 12 * D_B, float(ka[0]), float(kd[0]), steps)
+    el = time.time() - t0
+    nf = NXY * NXY * W
+    return {"value": nf * steps / el, "unit": "fluid-node-species updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"64x64x{W + 2} slit (widest of the workload), 1 species, {steps} steps, "
+                      f"FP64 stay form incl. its per-run set-up; {el:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the batched workload is one GPU's share "
+              f"(species/geometry sharding needs no exchange); --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1303_2470_amd import inputs, lbmp
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    lbmp.load_library()
+    flows, species, nf, ni = build_workload(lbmp, inputs)
+    total = args.warmup + args.steps
+    t0 = time.time()
+    mp = lbmp.mp_init(flows, species, lbmp.LBMP_FP32, total)
+    log(f"mp_init (incl. tile tuning): {time.time() - t0:.2f}s")
+    st = lbmp.mp_stats(mp, 0)
+    lbmp.mp_step_n(mp, args.warmup)
+    mp.stream.synchronize()
+    torch.cuda.synchronize()
+    # timed region: every step's propagation kernel bracketed by HIP events on
+    # the stream it runs on; the whole sequence bracketed as well
+    k_ms, tot_ms = lbmp.mp_profile_steps(mp, args.steps)
+    torch.cuda.synchronize()
+    upd_per_step = sum(f * N_SPECIES for f in nf)
+    value = upd_per_step * args.steps / (tot_ms / 1e3)
+    lat_nodes = sum(NXY * NXY * (W + 2) for W in WIDTHS)
+    # algorithmic bytes per launch: every quantity of every (node, species) read
+    # and written once (4 quantities x 4 B x 2), the same for the adsorbed
+    # quantities of interfacial nodes, and 16 B of flow data per fluid node
+    alg = sum(N_SPECIES * (32 * f + 32 * n) + 16 * f for f, n in zip(nf, ni))
+    k_avg_s = k_ms / 1e3 / args.steps
+    achieved = alg / k_avg_s / 1e9
+    traffic = traffic_record()
+    # accuracy and invariants of this run
+    out = lbmp.mp_vacf(mp, 3, total, 1)
+    mass_err = float(np.abs(out["mass"].sum(axis=1) - 1).max())
+    res = {
+        "metric": "moment-prop node-species updates/s",
+        "value": value,
+        "unit": "fluid-node-species updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tot_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched slits W=16,32,48,64 fluid layers x 64x64 lateral, "
+                               "64 species each (k_a,k_d log-uniform 1e-4..1e-1), D_b=1e-2, "
+                               "Poiseuille Pe=10, FP32 propagation + FP64 sums",
+                   "geometries": len(WIDTHS), "species_per_geometry": N_SPECIES,
+                   "fluid_nodes": int(sum(nf)), "interface_nodes": int(sum(ni)),
+                   "lattice_nodes": int(lat_nodes),
+                   "lattice_node_species_updates_per_s": lat_nodes * N_SPECIES * args.steps / (tot_ms / 1e3),
+                   "tile": {"K": st["tile_k"], "species_per_block": st["species_per_block"]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_mp_step", "kernel_avg_ms": k_avg_s * 1e3,
+                     "algorithmic_bytes_per_launch": alg},
+        "mass_error_max": mass_err,
+    }
+    mp.free()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

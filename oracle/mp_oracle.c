@@ -297,9 +297,13 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
 /* ---- steady BGK flow (Eq. 6) -------------------------------------------- */
 /* D3Q19 BGK, relaxation time tau, Guo forcing with force density rho*g,
  * half-way bounce-back at solid nodes, periodic otherwise. Starts at rest
- * with rho = 1. Every `check_every` steps the change of the velocity over one
- * step, max|u(t)-u(t-1)| / max|u(t)|, is compared with tol.
- * Outputs u[3][N] and rho[N] (zero on solid nodes).
+ * with rho = 1. The velocity u(t) = (sum f c + F/2)/rho is formed after every
+ * step; the reported velocity is the average of two consecutive steps,
+ * ubar(t) = (u(t) + u(t-1))/2, which removes the step-to-step sign flip of
+ * fluid nodes enclosed by solid (bounce-back returns all their momentum).
+ * Every `check_every` steps (t >= 2) the change max|ubar(t)-ubar(t-1)| /
+ * max|ubar(t)| is compared with tol.
+ * Outputs u[3][N] = ubar at the last step and rho[N] (zero on solid nodes).
  * Returns 0 when converged, 1 when max_steps was reached first, -1 when the
  * lattice has no fluid node. */
 static void bgk_macro(long N, const uint8_t* solid, const double* f, const double* g,
@@ -330,16 +334,18 @@ int orc_bgk(int nx, int ny, int nz, const uint8_t* solid, double tau, const doub
     if (nf == 0) return -1;
     double* f = (double*)calloc((size_t)Q19 * N, sizeof(double));
     double* fs = (double*)calloc((size_t)Q19 * N, sizeof(double));
-    double* uold = (double*)calloc(3 * (size_t)N, sizeof(double));
+    /* velocities of the last three steps: um2 = u(t-2), um1 = u(t-1), uc = u(t) */
+    double* um2 = (double*)calloc(3 * (size_t)N, sizeof(double));
+    double* um1 = (double*)calloc(3 * (size_t)N, sizeof(double));
+    double* uc = (double*)calloc(3 * (size_t)N, sizeof(double));
     for (long n = 0; n < N; ++n)
         if (!solid[n]) for (int i = 0; i < Q19; ++i) f[(long)i * N + n] = W[i];
+    bgk_macro(N, solid, f, g, rho, uc);
 
     int status = 1;
     double res = INFINITY;
     long step = 0;
     while (step < max_steps) {
-        int check = (check_every > 0) && ((step + 1) % check_every == 0);
-        if (check) bgk_macro(N, solid, f, g, rho, uold);
         /* collision with Guo forcing */
         #pragma omp parallel for schedule(static) if (N > 32768)
         for (long n = 0; n < N; ++n) {
@@ -373,22 +379,23 @@ int orc_bgk(int nx, int ny, int nz, const uint8_t* solid, double tau, const doub
             }
         }
         ++step;
-        if (check) {
-            bgk_macro(N, solid, f, g, rho, u);
+        double* t = um2; um2 = um1; um1 = uc; uc = t;
+        bgk_macro(N, solid, f, g, rho, uc);
+        if (check_every > 0 && step >= 2 && step % check_every == 0) {
             double du = 0.0, um = 0.0;
             for (long n = 0; n < 3 * N; ++n) {
-                double d = fabs(u[n] - uold[n]);
-                if (d > du) du = d;
-                if (fabs(u[n]) > um) um = fabs(u[n]);
+                double a = 0.5 * (uc[n] + um1[n]), b = 0.5 * (um1[n] + um2[n]);
+                if (fabs(a - b) > du) du = fabs(a - b);
+                if (fabs(a) > um) um = fabs(a);
             }
             res = um > 0.0 ? du / um : du;
             if (res < tol) { status = 0; break; }
         }
     }
-    bgk_macro(N, solid, f, g, rho, u);
+    for (long n = 0; n < 3 * N; ++n) u[n] = 0.5 * (uc[n] + um1[n]);
     *steps_done = step;
     *resid = res;
-    free(f); free(fs); free(uold);
+    free(f); free(fs); free(um2); free(um1); free(uc);
     return status;
 }
 

@@ -1,0 +1,1141 @@
+// Moment propagation with adsorption/desorption (Secs. II-III of the paper).
+//
+// Formulation on the device (the arithmetic of Eqs. 7, 9 and 10, rearranged
+// for FP32 storage; the CPU oracle keeps the literal form):
+//  * every propagated quantity X (density, first moments x, y, z) and its
+//    adsorbed counterpart are stored as deviations from a reference
+//    c_q * rho_ref (mobile) and c_q * Gamma_ref (adsorbed), where rho_ref and
+//    Gamma_ref are the Eq. 11 weights and c_q = 1 for the density and the mean
+//    velocity V_q for the first moments — the long-time limit of each field;
+//  * the receiving node pulls Y = sum_i X(r - c_i) p_i(r - c_i) with an FMA
+//    chain over a receiver-indexed table pin[i][r] = p_i(r - c_i);
+//  * X' = ((fma(-X, sigma, X) - p_a X + p_d X_ads) + c_q rho_ref src) + Y
+//    with sigma(r) = sum_i p_i(r) rounded once, and src(r) = sum_i pin_i(r) -
+//    sum_i p_i(r) formed exactly from the stored probabilities (zero wherever
+//    the Eq. 11 weights are stationary, e.g. slits with or without flow);
+//  * adsorption and desorption fluxes p_a X, p_d X_ads are rounded once and
+//    used on both sides, so Eqs. 9-10 exchange the same amount;
+//  * the VACF sum of Eq. 12 and the conserved totals are accumulated in FP64
+//    per block and reduced in a fixed order (bitwise reproducible).
+//
+// Batching: one launch advances every (geometry, species) pair. The logical
+// block list is (geometry, tile, species group) with the group fastest; a
+// tile is BLK lattice columns x K consecutive z-planes. Blocks are remapped
+// so each XCD receives a contiguous range of logical blocks. The state time
+// and ping-pong parity live in device memory, so a captured graph of steps
+// can be replayed.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "lbmp_internal.hpp"
+
+namespace lbmp {
+
+constexpr int BLK = 256;   // threads per block (4 waves)
+constexpr int NRED = 8;    // FP64 sums per (species, step)
+constexpr int SETUP_RED = 12;
+
+template <typename T>
+struct GeomDev {
+    int nx, ny, nz, S;
+    int64_t N, NI;
+    int pb, zb, ngrp;          // plane blocks, z blocks, species groups
+    int64_t blk0;              // first logical block of this geometry
+    const int8_t* cls;
+    const int32_t* slot;
+    const T* pin;              // [18][N]
+    const double* sig;         // [N] sum_i p_i(r), exact (FP64)
+    const T* src;              // [N]
+    const T* a;                // [3][N]
+    T* X0;                     // [S][4][N]
+    T* X1;                     // [S][4][N]
+    T* Xa;                     // [S][4][NI]
+    const T* coef;             // [S][4]
+    const T* prob;             // [S][2] = p_a, p_d
+    double* part;              // [S][ntile][NRED]
+    double* series;            // [Tmax][S][NRED], entry t-1 holds time t
+};
+
+struct Ctl {
+    int64_t t;     // time of the current state (1 after init)
+    int64_t tmax;  // last recordable time
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    // blockIdx b runs on XCD b % 8; give each XCD a contiguous logical range
+    int64_t per = nb / 8, rem = nb % 8;
+    int64_t x = b % 8, i = b / 8;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
+}
+
+__device__ __forceinline__ int modp(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Fixed-order sum of NRED doubles over the BLK threads of a block; thread k < NRED
+// of the block receives sum k in `res`.
+__device__ __forceinline__ void block_sum8(double (&v)[NRED], double* lds, double& res) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) lds[k * BLK + tid] = v[k];
+    __syncthreads();
+    const int k = tid >> 5, l = tid & 31;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < BLK / 32; ++j) s += lds[k * BLK + l * (BLK / 32) + j];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+    __syncthreads();
+    if (l == 0) lds[k] = s;
+    __syncthreads();
+    res = tid < NRED ? lds[tid] : 0.0;
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ int find_geom(const GeomDev<T>* G, int ng, int64_t lb) {
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (G[mid].blk0 <= lb) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Raw buffer access: a 128-bit resource per array (base, size in bytes); an
+// offset at or beyond the size reads 0 and drops the store, which is how
+// inactive lanes are masked without branches.
+constexpr int OOB = 0x7ffffff0;
+constexpr int RSRC_WORD3 = 0x00020000;  // gfx9-family raw buffer format word
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mkrsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, RSRC_WORD3);
+}
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int off) {
+    using v2u = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, off, 0, 0);
+}
+
+// Counter-based random bits for stochastic rounding: one 32-bit hash per
+// (node, step) seeds a xorshift32 stream (Marsaglia 2003) that is advanced once
+// per stored value; runs are reproducible.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    // integer finaliser of MurmurHash3
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t& s) {
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
+}
+// Round v to FP32 stochastically: up (in magnitude) with probability equal to
+// the discarded fraction of an FP32 unit in the last place, so the expected
+// stored value is v. Adds 29 random bits below the FP32 mantissa of the FP64
+// pattern and truncates them.
+__device__ __forceinline__ float sround(double v, uint32_t r) {
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    b = (b + (r & 0x1fffffffu)) & ~(uint64_t)0x1fffffffu;
+    return (float)__longlong_as_double((long long)b);
+}
+template <typename T> __device__ __forceinline__ T store_round(double v, uint32_t r);
+template <> __device__ __forceinline__ float store_round<float>(double v, uint32_t r) { return sround(v, r); }
+template <> __device__ __forceinline__ double store_round<double>(double v, uint32_t) { return v; }
+
+// One propagation step for every (geometry, species) pair. Loads and stores
+// are in the storage type T; the update itself is FP64 (an FMA chain for the
+// arrivals, the exact FP64 sum of the departures), rounded once on store —
+// stochastically for FP32 storage, so that no rounding direction repeats from
+// step to step.
+template <typename T, int K>
+__global__ void __launch_bounds__(BLK) k_mp_step(const GeomDev<T>* __restrict__ geoms, int ngeom,
+                                                 int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
+    __shared__ double lds[NRED * BLK];
+    constexpr int E = (int)sizeof(T);
+    T* const tag = nullptr;
+    double* const dtag = nullptr;
+    const int64_t lb = xcd_remap(blockIdx.x, nblocks);
+    const int gi = find_geom(geoms, ngeom, lb);
+    const GeomDev<T>& G = geoms[gi];
+    const int64_t local = lb - G.blk0;
+    const int grp = (int)(local % G.ngrp);
+    const int64_t tile = local / G.ngrp;
+    const int pbi = (int)(tile % G.pb), zbi = (int)(tile / G.pb);
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int N = (int)G.N, plane = nx * ny;
+    const int p = pbi * BLK + threadIdx.x;
+    const bool inplane = p < plane;
+    const int x = inplane ? p % nx : 0, y = inplane ? p / nx : 0;
+    const int z0 = zbi * K;
+    const int xm = modp(x - 1, nx), xp = modp(x + 1, nx), ym = modp(y - 1, ny), yp = modp(y + 1, ny);
+    // in-plane positions: 0 centre, 1 (x-1,y), 2 (x+1,y), 3 (x,y-1), 4 (x,y+1);
+    // diagonals: 0 (x-1,y-1), 1 (x+1,y+1), 2 (x-1,y+1), 3 (x+1,y-1)
+    const int o5[5] = {x + nx * y, xm + nx * y, xp + nx * y, x + nx * ym, x + nx * yp};
+    const int od[4] = {xm + nx * ym, xp + nx * yp, xm + nx * yp, xp + nx * ym};
+    int off5[K + 2][5], offd[K][4], offn[K], offa[K];
+#pragma unroll
+    for (int j = 0; j < K + 2; ++j) {
+        const int zo = modp(z0 - 1 + j, nz) * plane;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) off5[j][c] = inplane ? (zo + o5[c]) * E : OOB;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int zo = modp(z0 + j, nz) * plane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) offd[j][c] = inplane ? (zo + od[c]) * E : OOB;
+    }
+    const int64_t t = ctl->t;
+    // per-node link data (FP64 in registers); inactive nodes read zeros
+    bool act[K], isI[K];
+    double pin[K][NL], sig[K], src[K], av[K][3];
+    uint32_t rbase[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int n = modp(z0 + j, nz) * plane + o5[0];
+        act[j] = inplane && (z0 + j < nz) && G.cls[n] != 0;
+        const int sl = act[j] ? G.slot[n] : -1;
+        isI[j] = sl >= 0;
+        offn[j] = act[j] ? n * E : OOB;
+        offa[j] = isI[j] ? sl * E : OOB;
+        const int offn8 = act[j] ? n * 8 : OOB;
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            pin[j][k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * E), offn[j]);
+        sig[j] = bload(dtag, mkrsrc(G.sig, (int64_t)N * 8), offn8);
+        src[j] = (double)bload(tag, mkrsrc(G.src, (int64_t)N * E), offn[j]);
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            av[j][g] = (double)bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * E), offn[j]);
+        rbase[j] = hash32((uint32_t)n * 0x9e3779b9u ^ hash32((uint32_t)t ^ ((uint32_t)gi << 24)));
+    }
+    const T* Xin = (t & 1) ? G.X1 : G.X0;
+    T* Xout = (t & 1) ? G.X0 : G.X1;
+    const int s_begin = grp * gsz, s_end = min(G.S, s_begin + gsz);
+    const int64_t ntile = (int64_t)G.pb * G.zb;
+    const int64_t NI = G.NI;
+
+    for (int s = s_begin; s < s_end; ++s) {
+        const double pa = (double)G.prob[2 * s], pd = (double)G.prob[2 * s + 1];
+        uint32_t rs[K];  // random stream of (node, step, species)
+#pragma unroll
+        for (int j = 0; j < K; ++j) rs[j] = hash32(rbase[j] ^ ((uint32_t)s * 0x632be5abu)) | 1u;
+        double red[NRED];
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) red[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double cq = (double)G.coef[4 * s + q];
+            const int64_t f = 4 * s + q;
+            const auto rin = mkrsrc(Xin + f * N, (int64_t)N * E);
+            const auto rout = mkrsrc(Xout + f * N, (int64_t)N * E);
+            const auto rads = mkrsrc(G.Xa + f * NI, NI * E);
+            double v5[K + 2][5], vd[K][4], xa[K];
+#pragma unroll
+            for (int j = 0; j < K + 2; ++j)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) v5[j][c] = (double)bload(tag, rin, off5[j][c]);
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) vd[j][c] = (double)bload(tag, rin, offd[j][c]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) xa[j] = (double)bload(tag, rads, offa[j]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                // arrivals (Eq. 7): source node r - c_k of link k
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {
+                    const int dx = -lcx(k), dy = -lcy(k), dz = -lcz(k);
+                    double v;
+                    if (dz == 0 && dx != 0 && dy != 0) {
+                        const int c = (dx < 0 && dy < 0) ? 0 : (dx > 0 && dy > 0) ? 1 : (dx < 0) ? 2 : 3;
+                        v = vd[j][c];
+                    } else {
+                        const int c = dx < 0 ? 1 : dx > 0 ? 2 : dy < 0 ? 3 : dy > 0 ? 4 : 0;
+                        v = v5[j + 1 + dz][c];
+                    }
+                    acc = __builtin_fma(v, pin[j][k], acc);
+                }
+                const double xc = v5[j + 1][0];
+                const double fa = isI[j] ? pa * xc : 0.0;   // adsorption (Eq. 9)
+                const double fd = pd * xa[j];               // desorption (Eq. 10); xa = 0 off the interface
+                double nv = __builtin_fma(-xc, sig[j], xc); // the part that stays (Eq. 7)
+                nv = __builtin_fma(cq, src[j], (nv - fa) + fd) + acc;
+                const uint32_t r1 = xorshift32(rs[j]);
+                bstore(store_round<T>(nv, r1), rout, offn[j]);
+                bstore(store_round<T>((xa[j] + fa) - fd, (r1 >> 3) | (r1 << 29)), rads, offa[j]);
+                const double xd = act[j] ? xc : 0.0;
+                if (q == 0) {
+                    red[3] += xd;
+                    red[7] += xa[j];
+                } else {
+                    red[q - 1] = __builtin_fma(xd, av[j][q - 1], red[q - 1]);
+                    red[3 + q] += xd + xa[j];
+                }
+            }
+        }
+        double r;
+        block_sum8(red, lds, r);
+        if (threadIdx.x < NRED)
+            G.part[((int64_t)s * ntile + tile) * NRED + threadIdx.x] = r;
+    }
+}
+
+// Sum the block partials of every (geometry, species) into the series at the
+// current time, in a fixed order; then advance the state time.
+template <typename T>
+__global__ void k_mp_reduce(const GeomDev<T>* __restrict__ geoms, int ngeom,
+                            const int32_t* __restrict__ work, int nwork, Ctl* __restrict__ ctl) {
+    const int w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    const int64_t t = ctl->t;
+    if (w < nwork) {
+        const int gi = work[2 * w], s = work[2 * w + 1];
+        const GeomDev<T>& G = geoms[gi];
+        const int64_t ntile = (int64_t)G.pb * G.zb;
+        const double* P = G.part + (int64_t)s * ntile * NRED;
+        double acc[NRED];
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+        for (int64_t i = lane; i < ntile; i += 64)
+#pragma unroll
+            for (int k = 0; k < NRED; ++k) acc[k] += P[i * NRED + k];
+#pragma unroll
+        for (int k = 0; k < NRED; ++k)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+        if (lane < NRED && t <= ctl->tmax) {
+            double v = acc[0];
+#pragma unroll
+            for (int k = 1; k < NRED; ++k)
+                if (lane == k) v = acc[k];
+            G.series[((t - 1) * G.S + s) * NRED + lane] = v;
+        }
+    }
+}
+
+__global__ void k_advance(Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t += 1;
+}
+
+// ------------------------------------------------------------------ set-up
+// Link probabilities of Eq. 8 (local equilibrium, Q = 1), FP64, per node and
+// link; zero on solid nodes and for links into solid nodes.
+__global__ void k_pout(const int8_t* __restrict__ cls, const double* __restrict__ u, int nx, int ny,
+                       int nz, double lam, double* __restrict__ pout) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+    const double ux = u[n], uy = u[N + n], uz = u[2 * N + n];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    for (int k = 0; k < NL; ++k) {
+        double p = 0.0;
+        if (cls[n] != 0) {
+            int64_t m = modp(x + lcx(k), nx) + (int64_t)nx * (modp(y + lcy(k), ny) + (int64_t)ny * modp(z + lcz(k), nz));
+            if (cls[m] != 0) {
+                double cu = lcx(k) * ux + lcy(k) * uy + lcz(k) * uz;
+                p = lw(k) * (0.5 * lam + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            }
+        }
+        pout[(int64_t)k * N + n] = p;
+    }
+}
+
+// Stored tables and per-node set-up values. Sums of stored (rounded) link
+// probabilities are formed in FP64, so sigma and src describe exactly the
+// chain the stored table propagates.
+// setup partials per block: [0..2] sum_r a_g, [3..5] sum_r sum_i p_i c_ig^2,
+// [6] min p_i, [7] max |u|, [8] min stay (bulk), [9] min stay (interface),
+// [10] number of fluid nodes, [11] unused.
+template <typename T>
+__global__ void k_links(const int8_t* __restrict__ cls, const double* __restrict__ pout,
+                        const double* __restrict__ u, int nx, int ny, int nz, T* __restrict__ pin,
+                        double* __restrict__ sig, T* __restrict__ src, T* __restrict__ a,
+                        double* __restrict__ b64, double* __restrict__ src64,
+                        double* __restrict__ part) {
+    __shared__ double lds[SETUP_RED * BLK];
+    const int64_t N = (int64_t)nx * ny * nz;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[SETUP_RED] = {0, 0, 0, 0, 0, 0, INFINITY, 0.0, INFINITY, INFINITY, 0, 0};
+    if (n < N) {
+        const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        const bool fl = cls[n] != 0;
+        double sout = 0.0, sin = 0.0, ag[3] = {0, 0, 0}, bg[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+        for (int k = 0; k < NL; ++k) {
+            const double po = (double)(T)pout[(int64_t)k * N + n];
+            sout += po;
+            ag[0] += po * lcx(k);
+            ag[1] += po * lcy(k);
+            ag[2] += po * lcz(k);
+            c2[0] += po * lcx(k) * lcx(k);
+            c2[1] += po * lcy(k) * lcy(k);
+            c2[2] += po * lcz(k) * lcz(k);
+            int64_t m = modp(x - lcx(k), nx) + (int64_t)nx * (modp(y - lcy(k), ny) + (int64_t)ny * modp(z - lcz(k), nz));
+            const T pt = fl ? (T)pout[(int64_t)k * N + m] : T(0);
+            pin[(int64_t)k * N + n] = pt;
+            sin += (double)pt;
+            bg[0] += (double)pt * lcx(k);
+            bg[1] += (double)pt * lcy(k);
+            bg[2] += (double)pt * lcz(k);
+            if (fl && cls[m] != 0) v[6] = fmin(v[6], pout[(int64_t)k * N + n]);
+        }
+        sig[n] = fl ? sout : 0.0;
+        // arrivals minus departures of the stored table, both summed exactly:
+        // zero wherever the Eq. 11 weights are stationary for that table
+        const double s64 = fl ? sin - sout : 0.0;
+        src[n] = (T)s64;
+        src64[n] = s64;
+        for (int g = 0; g < 3; ++g) {
+            a[(int64_t)g * N + n] = fl ? (T)ag[g] : T(0);
+            b64[(int64_t)g * N + n] = fl ? bg[g] : 0.0;
+        }
+        if (fl) {
+            for (int g = 0; g < 3; ++g) {
+                v[g] = ag[g];
+                v[3 + g] = c2[g];
+            }
+            const double uu = sqrt(u[n] * u[n] + u[N + n] * u[N + n] + u[2 * N + n] * u[2 * N + n]);
+            v[7] = uu;
+            if (cls[n] == 2) v[9] = 1.0 - sout; else v[8] = 1.0 - sout;
+            v[10] = 1.0;
+        }
+    }
+    const int tid = threadIdx.x;
+    for (int k = 0; k < SETUP_RED; ++k) lds[k * BLK + tid] = v[k];
+    __syncthreads();
+    if (tid < SETUP_RED) {
+        double r = lds[tid * BLK];
+        for (int j = 1; j < BLK; ++j) {
+            double w = lds[tid * BLK + j];
+            if (tid == 6 || tid == 8 || tid == 9) r = fmin(r, w);
+            else if (tid == 7) r = fmax(r, w);
+            else r += w;
+        }
+        part[(int64_t)blockIdx.x * SETUP_RED + tid] = r;
+    }
+}
+
+__global__ void k_setup_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= SETUP_RED || blockIdx.x != 0) return;
+    double r = part[k];
+    for (int b = 1; b < nb; ++b) {
+        double w = part[(int64_t)b * SETUP_RED + k];
+        if (k == 6 || k == 8 || k == 9) r = fmin(r, w);
+        else if (k == 7) r = fmax(r, w);
+        else r += w;
+    }
+    out[k] = r;
+}
+
+// State at t = 1 (deviations): density rho_ref*src; first moments
+// rho_ref*(b_q - V_q); adsorbed density 0; adsorbed first moments -V_q Gamma_ref.
+template <typename T>
+__global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __restrict__ ilist,
+                             int64_t N, int64_t NI, int S, const double* __restrict__ spc,
+                             const double* __restrict__ b64, const double* __restrict__ src64,
+                             T* __restrict__ X, T* __restrict__ Xa) {
+    // spc per species: rho_ref, Gamma_ref, V0, V1, V2
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    const double rr = spc[5 * s], gr = spc[5 * s + 1];
+    if (n < N) {
+        const bool fl = cls[n] != 0;
+        X[(int64_t)(4 * s) * N + n] = fl ? (T)(rr * src64[n]) : T(0);
+        for (int q = 1; q < 4; ++q)
+            X[(int64_t)(4 * s + q) * N + n] = fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q]) : T(0);
+    }
+    if (n < NI) {
+        Xa[(int64_t)(4 * s) * NI + n] = T(0);
+        for (int q = 1; q < 4; ++q) Xa[(int64_t)(4 * s + q) * NI + n] = (T)(-spc[5 * s + 1 + q] * gr);
+    }
+}
+
+// Time series of Z_g and D_g (discrete Eq. 3 about the mean drift) for one
+// geometry, one thread per (species, direction), compensated summation.
+// Z(t) = V^2 + sum_r dP a - E(t) V, where E(t) = sum dP + sum dP_ads is the
+// total of the first-moment deviations (zero in exact arithmetic; the term
+// removes the rounding drift of the stored total from the VACF).
+__global__ void k_vacf_series(const double* __restrict__ series, int S, int64_t T, int64_t stride,
+                              const double* __restrict__ spc0, double* __restrict__ Zo,
+                              double* __restrict__ Do) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * S) return;
+    const int s = i / 3, g = i % 3;
+    const double V = spc0[4 * s + g];
+    const double z0 = spc0[(int64_t)S * 4 + 3 * s + g];
+    double* Z = Zo + (int64_t)i * stride;
+    double* D = Do + (int64_t)i * stride;
+    Z[0] = z0;
+    double sum = 0.5 * (z0 - V * V), comp = 0.0;
+    D[0] = sum;
+    for (int64_t t = 1; t <= T; ++t) {
+        const double* e = series + ((t - 1) * S + s) * NRED;
+        const double c = e[g] - e[4 + g] * V;
+        Z[t] = V * V + c;
+        const double tt = sum + c;
+        comp += fabs(sum) >= fabs(c) ? (sum - tt) + c : (c - tt) + sum;
+        sum = tt;
+        D[t] = sum + comp;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+struct TuneKey {
+    int prec;
+    std::vector<int64_t> shape;
+    bool operator<(const TuneKey& o) const { return std::tie(prec, shape) < std::tie(o.prec, o.shape); }
+};
+struct TuneVal {
+    int K, gsz;
+};
+static std::map<TuneKey, TuneVal> g_tune_cache;
+
+struct GeomHost {
+    const lbmp_flow* flow;
+    int S;
+    int64_t N, NI, nf;
+    double lam;
+    std::vector<double> pa, pd, rho_ref, gam_ref;
+    double A[3], B[3];
+    double min_p, max_u, min_stay_bulk, min_stay_iface, pa_max;
+    std::vector<double> V, Z0;  // [S][3]
+    int64_t ntile_max;
+    // device buffers
+    void *pin, *sig, *src, *a, *X0, *X1, *Xa, *coef, *prob;
+    double *part, *series, *spc, *spc0, *zout, *dout;
+};
+
+}  // namespace lbmp
+
+struct lbmp_mp {
+    uint32_t magic;
+    int prec, ngeom;
+    int64_t tmax, steps;
+    hipStream_t stream;
+    std::vector<lbmp::GeomHost> g;
+    void* geoms_dev;
+    lbmp::Ctl* ctl;
+    int32_t* work;
+    int nwork;
+    double* setup_tmp;
+    int K, gsz;
+    int64_t nblocks;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace lbmp {
+namespace {
+
+constexpr int GRAPH_CHUNK = 64;
+
+int64_t ntile_for(const lbmp_flow* f, int K) {
+    int64_t pb = ((int64_t)f->nx * f->ny + BLK - 1) / BLK;
+    int64_t zb = (f->nz + K - 1) / K;
+    return pb * zb;
+}
+
+int64_t setup_doubles(int64_t N) { return 22 * N + ((N + BLK - 1) / BLK) * SETUP_RED + SETUP_RED; }
+
+template <typename T>
+void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
+    const int64_t N = g.N, NIa = std::max<int64_t>(g.NI, 1);
+    const size_t S = (size_t)g.S;
+    g.pin = c.take<T>(18 * N);
+    g.sig = c.take<double>(N);
+    g.src = c.take<T>(N);
+    g.a = c.take<T>(3 * N);
+    g.X0 = c.take<T>(S * 4 * N);
+    g.X1 = c.take<T>(S * 4 * N);
+    g.Xa = c.take<T>(S * 4 * NIa);
+    g.coef = c.take<T>(S * 4);
+    g.prob = c.take<T>(S * 2);
+    g.part = c.take<double>(S * g.ntile_max * NRED);
+    g.series = c.take<double>((size_t)std::max<int64_t>(tmax, 1) * S * NRED);
+    g.spc = c.take<double>(S * 5);
+    g.spc0 = c.take<double>(S * 7);
+    g.zout = c.take<double>(S * 3 * (tmax + 1));
+    g.dout = c.take<double>(S * 3 * (tmax + 1));
+}
+
+// Carves the whole workspace; with a null base it only measures.
+lbmp_status carve_all(lbmp_mp* h, Carver& c) {
+    h->geoms_dev = c.take<char>(sizeof(GeomDev<double>) * h->ngeom);
+    h->ctl = c.take<Ctl>(1);
+    int64_t setup = 0;
+    int nw = 0;
+    for (auto& g : h->g) {
+        if (h->prec == LBMP_FP32) carve_geom<float>(g, c, h->tmax); else carve_geom<double>(g, c, h->tmax);
+        setup = std::max(setup, setup_doubles(g.N));
+        nw += g.S;
+    }
+    h->setup_tmp = c.take<double>(setup);
+    h->work = c.take<int32_t>(2 * (size_t)nw);
+    h->nwork = nw;
+    return LBMP_OK;
+}
+
+lbmp_status resolve_lambda(const lbmp_species& sp, double* lam) {
+    bool has_db = std::isfinite(sp.D_b), has_dl = std::isfinite(sp.Delta);
+    if (has_db == has_dl) return fail(LBMP_EINVAL, "give exactly one of D_b and Delta (the other NaN)");
+    if (has_db) {
+        if (!(sp.D_b > 0)) return fail(LBMP_EINVAL, "D_b must be positive");
+        *lam = 12.0 * sp.D_b;
+    } else {
+        if (!(sp.Delta >= 0.0 && sp.Delta < 1.0)) return fail(LBMP_EINVAL, "Delta must be in [0, 1)");
+        *lam = 3.0 * (1.0 - sp.Delta);
+    }
+    return LBMP_OK;
+}
+
+lbmp_status validate_species(const lbmp_species& sp, int gi) {
+    if (sp.n_species < 1) return fail(LBMP_EINVAL, "geometry %d: n_species must be >= 1", gi);
+    if (!sp.k_a || !sp.k_d) return fail(LBMP_EINVAL, "geometry %d: rate arrays are NULL", gi);
+    for (int s = 0; s < sp.n_species; ++s) {
+        if (!(sp.k_a[s] >= 0.0) || !std::isfinite(sp.k_a[s]))
+            return fail(LBMP_EINVAL, "geometry %d: k_a[%d] must be finite and >= 0", gi, s);
+        if (!(sp.k_d[s] > 0.0 && sp.k_d[s] <= 1.0))
+            return fail(LBMP_EINVAL,
+                        "geometry %d: k_d[%d] must be in (0, 1] (irreversible sorption has no equilibrium VACF)",
+                        gi, s);
+    }
+    double lam;
+    return resolve_lambda(sp, &lam);
+}
+
+lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom, int precision,
+                     int64_t tmax) {
+    auto* h = new lbmp_mp();
+    h->magic = MP_MAGIC;
+    h->prec = precision;
+    h->ngeom = n_geom;
+    h->tmax = tmax;
+    h->steps = 0;
+    h->g.resize(n_geom);
+    for (int gi = 0; gi < n_geom; ++gi) {
+        GeomHost& g = h->g[gi];
+        g.flow = flows[gi];
+        g.S = species[gi].n_species;
+        g.N = g.flow->N;
+        g.NI = g.flow->ni;
+        g.nf = g.flow->nf;
+        g.ntile_max = ntile_for(g.flow, 1);
+    }
+    return h;
+}
+
+template <typename T>
+void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
+    auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
+    dim3 grid((unsigned)h->nblocks);
+    switch (h->K) {
+        case 1: k_mp_step<T, 1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl); break;
+        default: k_mp_step<T, 2><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl); break;
+    }
+}
+
+template <typename T>
+void launch_step_tail(lbmp_mp* h, hipStream_t s) {
+    auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
+    k_mp_reduce<T><<<(unsigned)((h->nwork + 3) / 4), 256, 0, s>>>(G, h->ngeom, h->work, h->nwork, h->ctl);
+    k_advance<<<1, 64, 0, s>>>(h->ctl);
+}
+
+template <typename T>
+void launch_step(lbmp_mp* h, hipStream_t s) {
+    launch_step_kernel<T>(h, s);
+    launch_step_tail<T>(h, s);
+}
+
+void do_steps(lbmp_mp* h, int64_t n, hipStream_t s) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (h->prec == LBMP_FP32) launch_step<float>(h, s); else launch_step<double>(h, s);
+    }
+}
+
+// Fill the device geometry table for the current (K, gsz).
+template <typename T>
+lbmp_status upload_geoms(lbmp_mp* h) {
+    std::vector<GeomDev<T>> v(h->ngeom);
+    int64_t blk = 0;
+    for (int gi = 0; gi < h->ngeom; ++gi) {
+        GeomHost& g = h->g[gi];
+        const lbmp_flow* f = g.flow;
+        GeomDev<T>& d = v[gi];
+        d.nx = f->nx; d.ny = f->ny; d.nz = f->nz; d.S = g.S;
+        d.N = g.N; d.NI = std::max<int64_t>(g.NI, 1);
+        d.pb = (int)(((int64_t)f->nx * f->ny + BLK - 1) / BLK);
+        d.zb = (f->nz + h->K - 1) / h->K;
+        d.ngrp = (g.S + h->gsz - 1) / h->gsz;
+        d.blk0 = blk;
+        blk += (int64_t)d.pb * d.zb * d.ngrp;
+        d.cls = f->d.cls; d.slot = f->d.slot;
+        d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
+        d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
+        d.coef = (const T*)g.coef; d.prob = (const T*)g.prob;
+        d.part = g.part; d.series = g.series;
+    }
+    h->nblocks = blk;
+    LBMP_HIP(hipMemcpyAsync(h->geoms_dev, v.data(), sizeof(GeomDev<T>) * v.size(), hipMemcpyHostToDevice, h->stream));
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    return LBMP_OK;
+}
+
+lbmp_status upload(lbmp_mp* h) { return h->prec == LBMP_FP32 ? upload_geoms<float>(h) : upload_geoms<double>(h); }
+
+// Pick (K, species per block) by timing a few steps of each candidate on the
+// set-up tables before the state exists. Results are cached per
+// (precision, shapes) for the life of the process.
+lbmp_status autotune(lbmp_mp* h) {
+    TuneKey key{h->prec, {}};
+    int64_t work = 0;
+    int maxS = 0;
+    for (auto& g : h->g) {
+        key.shape.insert(key.shape.end(), {g.flow->nx, g.flow->ny, g.flow->nz, g.S});
+        work += g.nf * g.S;
+        maxS = std::max(maxS, g.S);
+    }
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        h->K = it->second.K;
+        h->gsz = it->second.gsz;
+        return upload(h);
+    }
+    if (work < (1 << 16)) {  // launch-bound sizes: one block per tile, all species
+        h->K = 1;
+        h->gsz = maxS;
+        g_tune_cache[key] = {h->K, h->gsz};
+        return upload(h);
+    }
+    std::vector<std::pair<int, int>> cand;
+    for (int K : {1, 2})
+        for (int gs : {1, 2, 4, 8, 16, 32, 64})
+            if (gs <= maxS || gs == 1) cand.push_back({K, gs});
+    hipEvent_t e0, e1;
+    LBMP_HIP(hipEventCreate(&e0));
+    LBMP_HIP(hipEventCreate(&e1));
+    float best = INFINITY;
+    TuneVal bv{2, 8};
+    const int reps = 3;
+    for (auto [K, gs] : cand) {
+        h->K = K;
+        h->gsz = gs;
+        lbmp_status st = upload(h);
+        if (st != LBMP_OK) return st;
+        do_steps(h, 1, h->stream);
+        LBMP_HIP(hipEventRecord(e0, h->stream));
+        do_steps(h, reps, h->stream);
+        LBMP_HIP(hipEventRecord(e1, h->stream));
+        LBMP_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        LBMP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bv = {K, gs};
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->K = bv.K;
+    h->gsz = bv.gsz;
+    g_tune_cache[key] = bv;
+    return upload(h);
+}
+
+// Link tables for one geometry (and the FP64 per-node values of the initial
+// state in setup_tmp).
+template <typename T>
+lbmp_status build_links(lbmp_mp* h, GeomHost& g, hipStream_t s, double* fin_host) {
+    const lbmp_flow* f = g.flow;
+    const int64_t N = f->N;
+    double* pout = h->setup_tmp;
+    double* b64 = pout + 18 * N;
+    double* src64 = b64 + 3 * N;
+    double* part = src64 + N;
+    const unsigned nb = (unsigned)((N + BLK - 1) / BLK);
+    double* fin = part + (size_t)nb * SETUP_RED;
+    k_pout<<<nb, BLK, 0, s>>>(f->d.cls, f->d.u, f->nx, f->ny, f->nz, g.lam, pout);
+    k_links<T><<<nb, BLK, 0, s>>>(f->d.cls, pout, f->d.u, f->nx, f->ny, f->nz, (T*)g.pin, (double*)g.sig,
+                                  (T*)g.src, (T*)g.a, b64, src64, part);
+    k_setup_final<<<1, 64, 0, s>>>(part, nb, fin);
+    LBMP_HIP(hipGetLastError());
+    if (fin_host) {
+        LBMP_HIP(hipMemcpyAsync(fin_host, fin, SETUP_RED * 8, hipMemcpyDeviceToHost, s));
+        LBMP_HIP(hipStreamSynchronize(s));
+    }
+    return LBMP_OK;
+}
+
+// Species constants: Eq. 11 weights, mean velocity, Z(0), probabilities.
+template <typename T>
+lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStream_t s) {
+    const int S = g.S;
+    for (int k = 0; k < 3; ++k) {
+        g.A[k] = r[k];
+        g.B[k] = r[3 + k];
+    }
+    g.min_p = r[6];
+    g.max_u = r[7];
+    g.min_stay_bulk = r[8];
+    g.min_stay_iface = r[9];
+    std::vector<double> spc(S * 5), spc0(S * 7, 0.0);
+    std::vector<T> coef(S * 4), prob(S * 2);
+    g.rho_ref.resize(S);
+    g.gam_ref.resize(S);
+    g.V.assign(3 * S, 0.0);
+    g.Z0.assign(3 * S, 0.0);
+    g.pa_max = 0.0;
+    for (int sp = 0; sp < S; ++sp) {
+        const double Kr = g.pa[sp] / g.pd[sp];
+        const double Zp = (double)g.nf + (double)g.NI * Kr;
+        const double rr = 1.0 / Zp, gr = Kr / Zp;
+        g.rho_ref[sp] = rr;
+        g.gam_ref[sp] = gr;
+        spc[5 * sp] = rr;
+        spc[5 * sp + 1] = gr;
+        for (int k = 0; k < 3; ++k) {
+            g.V[3 * sp + k] = rr * g.A[k];
+            g.Z0[3 * sp + k] = rr * g.B[k];
+            spc[5 * sp + 2 + k] = g.V[3 * sp + k];
+            spc0[4 * sp + k] = g.V[3 * sp + k];
+            spc0[(size_t)S * 4 + 3 * sp + k] = g.Z0[3 * sp + k];
+        }
+        coef[4 * sp] = (T)rr;
+        for (int k = 0; k < 3; ++k) coef[4 * sp + 1 + k] = (T)(rr * g.V[3 * sp + k]);
+        prob[2 * sp] = (T)g.pa[sp];
+        prob[2 * sp + 1] = (T)g.pd[sp];
+        if (g.NI > 0) g.pa_max = std::max(g.pa_max, g.pa[sp]);
+    }
+    const double min_stay = std::min(g.min_stay_bulk, g.min_stay_iface - g.pa_max);
+    if (min_stay < 0.0)
+        return fail(LBMP_EPROB, "negative stay probability %.3e (sum p_i + p_a > 1)", min_stay);
+    LBMP_HIP(hipMemcpyAsync(g.spc, spc.data(), spc.size() * 8, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.spc0, spc0.data(), spc0.size() * 8, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.coef, coef.data(), coef.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.prob, prob.data(), prob.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    return LBMP_OK;
+}
+
+// The state at t = 1 lives in the odd buffer X1; X0 starts at zero.
+template <typename T>
+lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
+    const int64_t N = g.N;
+    double* b64 = h->setup_tmp + 18 * N;
+    double* src64 = b64 + 3 * N;
+    LBMP_HIP(hipMemsetAsync(g.X0, 0, (size_t)g.S * 4 * N * sizeof(T), s));
+    dim3 grid((unsigned)((std::max<int64_t>(N, g.NI) + BLK - 1) / BLK), (unsigned)g.S);
+    k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64,
+                                         (T*)g.X1, (T*)g.Xa);
+    LBMP_HIP(hipGetLastError());
+    return LBMP_OK;
+}
+
+template <typename T>
+lbmp_status setup_all(lbmp_mp* h, hipStream_t s) {
+    double r[SETUP_RED];
+    for (auto& g : h->g) {
+        lbmp_status st = build_links<T>(h, g, s, r);
+        if (st != LBMP_OK) return st;
+        st = species_constants<T>(h, g, r, s);
+        if (st != LBMP_OK) return st;
+        LBMP_HIP(hipMemsetAsync(g.X0, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
+        LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
+        LBMP_HIP(hipMemsetAsync(g.Xa, 0, (size_t)g.S * 4 * std::max<int64_t>(g.NI, 1) * sizeof(T), s));
+    }
+    std::vector<int32_t> work;
+    for (int gi = 0; gi < h->ngeom; ++gi)
+        for (int sp = 0; sp < h->g[gi].S; ++sp) {
+            work.push_back(gi);
+            work.push_back(sp);
+        }
+    LBMP_HIP(hipMemcpyAsync(h->work, work.data(), work.size() * 4, hipMemcpyHostToDevice, s));
+    Ctl c0{1, h->tmax};
+    LBMP_HIP(hipMemcpyAsync(h->ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    lbmp_status st = autotune(h);
+    if (st != LBMP_OK) return st;
+    // tuning advanced the device time and wrote the buffers: start over
+    LBMP_HIP(hipMemcpyAsync(h->ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    for (auto& g : h->g) {
+        st = build_links<T>(h, g, s, nullptr);
+        if (st != LBMP_OK) return st;
+        st = init_state<T>(h, g, s);
+        if (st != LBMP_OK) return st;
+    }
+    LBMP_HIP(hipStreamSynchronize(s));
+    return LBMP_OK;
+}
+
+lbmp_status check_mp(const lbmp_mp* h) {
+    if (!h || h->magic != MP_MAGIC) return fail(LBMP_ESTATE, "invalid moment-propagation handle");
+    return LBMP_OK;
+}
+
+}  // namespace
+}  // namespace lbmp
+
+using namespace lbmp;
+
+extern "C" lbmp_status mp_workspace_bytes(const lbmp_flow* const* flows, const lbmp_species* species,
+                                          int n_geom, int precision, int64_t max_steps_recorded,
+                                          size_t* bytes) {
+    if (!flows || !species || n_geom < 1 || !bytes) return fail(LBMP_EINVAL, "bad arguments");
+    if (precision != LBMP_FP32 && precision != LBMP_FP64) return fail(LBMP_EINVAL, "precision must be 32 or 64");
+    if (max_steps_recorded < 0) return fail(LBMP_EINVAL, "max_steps_recorded must be >= 0");
+    for (int gi = 0; gi < n_geom; ++gi) {
+        if (!flows[gi] || flows[gi]->magic != FLOW_MAGIC) return fail(LBMP_ESTATE, "flow %d is not a valid handle", gi);
+        if (species[gi].n_species < 1) return fail(LBMP_EINVAL, "geometry %d: n_species must be >= 1", gi);
+        // fields are addressed with 32-bit byte offsets
+        const int64_t es = precision == LBMP_FP32 ? 4 : 8;
+        if (flows[gi]->N * es > (int64_t)INT32_MAX)
+            return fail(LBMP_EINVAL, "geometry %d: %lld nodes exceed the per-field limit of %lld", gi,
+                        (long long)flows[gi]->N, (long long)(INT32_MAX / es));
+    }
+    lbmp_mp* h = make_handle(flows, species, n_geom, precision, max_steps_recorded);
+    Carver c(nullptr, ~size_t(0));
+    carve_all(h, c);
+    *bytes = c.off;
+    delete h;
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
+                               int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
+                               void* hip_stream, lbmp_mp** out) {
+    if (!out) return fail(LBMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    lbmp_status st = mp_workspace_bytes(flows, species, n_geom, precision, max_steps_recorded, &need);
+    if (st != LBMP_OK) return st;
+    if (!dev_ws || ws_bytes < need) return fail(LBMP_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+    for (int gi = 0; gi < n_geom; ++gi) {
+        st = validate_species(species[gi], gi);
+        if (st != LBMP_OK) return st;
+    }
+    lbmp_mp* h = make_handle(flows, species, n_geom, precision, max_steps_recorded);
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    for (int gi = 0; gi < n_geom; ++gi) {
+        GeomHost& g = h->g[gi];
+        resolve_lambda(species[gi], &g.lam);
+        g.pa.assign(species[gi].k_a, species[gi].k_a + g.S);  // p_a = k_a dt / dx
+        g.pd.assign(species[gi].k_d, species[gi].k_d + g.S);  // p_d = k_d dt
+    }
+    Carver c(dev_ws, ws_bytes);
+    carve_all(h, c);
+    if (!c.fits()) {
+        delete h;
+        return fail(LBMP_ENOMEM, "workspace too small");
+    }
+    st = precision == LBMP_FP32 ? setup_all<float>(h, h->stream) : setup_all<double>(h, h->stream);
+    if (st != LBMP_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_step_n(lbmp_mp* h, int64_t n_steps) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (n_steps < 0) return fail(LBMP_EINVAL, "n_steps must be >= 0");
+    if (h->steps + n_steps > h->tmax)
+        return fail(LBMP_ESTATE, "%lld steps would exceed max_steps_recorded = %lld",
+                    (long long)(h->steps + n_steps), (long long)h->tmax);
+    hipStream_t s = h->stream;
+    int64_t left = n_steps;
+    // replay a captured chunk of steps when the stream can be captured
+    if (s != nullptr && left >= 2 * GRAPH_CHUNK) {
+        if (!h->gexec) {
+            LBMP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            do_steps(h, GRAPH_CHUNK, s);
+            LBMP_HIP(hipStreamEndCapture(s, &h->graph));
+            LBMP_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+        }
+        while (left >= GRAPH_CHUNK) {
+            LBMP_HIP(hipGraphLaunch(h->gexec, s));
+            left -= GRAPH_CHUNK;
+        }
+    }
+    do_steps(h, left, s);
+    LBMP_HIP(hipGetLastError());
+    h->steps += n_steps;
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_steps_done(const lbmp_mp* h, int64_t* t) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (!t) return fail(LBMP_EINVAL, "t is NULL");
+    *t = h->steps;
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* Z, double* D,
+                               double* mass, double* vbar) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (geom < 0 || geom >= h->ngeom) return fail(LBMP_EINVAL, "geometry index %d out of range", geom);
+    if (t0 < 0 || count < 0 || t0 + count - 1 > h->steps)
+        return fail(LBMP_EINVAL, "times %lld..%lld not recorded (0..%lld)", (long long)t0,
+                    (long long)(t0 + count - 1), (long long)h->steps);
+    GeomHost& g = h->g[geom];
+    hipStream_t s = h->stream;
+    const int S = g.S;
+    const int64_t stride = h->tmax + 1;
+    if ((Z || D) && count > 0) {
+        k_vacf_series<<<(3 * S + 63) / 64, 64, 0, s>>>(g.series, S, h->steps, stride, g.spc0, g.zout, g.dout);
+        LBMP_HIP(hipGetLastError());
+        if (Z)
+            LBMP_HIP(hipMemcpy2DAsync(Z, count * 8, g.zout + t0, stride * 8, count * 8, 3 * (size_t)S,
+                                      hipMemcpyDeviceToHost, s));
+        if (D)
+            LBMP_HIP(hipMemcpy2DAsync(D, count * 8, g.dout + t0, stride * 8, count * 8, 3 * (size_t)S,
+                                      hipMemcpyDeviceToHost, s));
+    }
+    std::vector<double> last;
+    if (mass && h->steps > 0) {
+        last.resize((size_t)S * NRED);
+        LBMP_HIP(hipMemcpyAsync(last.data(), g.series + (h->steps - 1) * S * NRED, last.size() * 8,
+                                hipMemcpyDeviceToHost, s));
+    }
+    LBMP_HIP(hipStreamSynchronize(s));
+    if (mass)
+        for (int sp = 0; sp < S; ++sp) {
+            mass[2 * sp] = g.rho_ref[sp] * (double)g.nf + (last.empty() ? 0.0 : last[sp * NRED + 3]);
+            mass[2 * sp + 1] = g.gam_ref[sp] * (double)g.NI + (last.empty() ? 0.0 : last[sp * NRED + 7]);
+        }
+    if (vbar)
+        for (int i = 0; i < 3 * S; ++i) vbar[i] = g.V[i];
+    const size_t n = (size_t)3 * S * count;
+    for (size_t i = 0; i < n; ++i)
+        if ((Z && !std::isfinite(Z[i])) || (D && !std::isfinite(D[i])))
+            return fail(LBMP_ENUMERIC, "non-finite value in the recorded series");
+    if (mass)
+        for (int i = 0; i < 2 * S; ++i)
+            if (!std::isfinite(mass[i])) return fail(LBMP_ENUMERIC, "non-finite total probability");
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_stats(const lbmp_mp* h, int geom, lbmp_stats* out) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (geom < 0 || geom >= h->ngeom || !out) return fail(LBMP_EINVAL, "bad geometry index or output");
+    const GeomHost& g = h->g[geom];
+    out->n_nodes = g.N;
+    out->n_fluid = g.nf;
+    out->n_iface = g.NI;
+    out->lambda = g.lam;
+    out->min_p = g.min_p;
+    out->max_cell_peclet = g.max_u / (g.lam / 12.0);
+    out->min_stay = std::min(g.min_stay_bulk, g.min_stay_iface - g.pa_max);
+    for (int k = 0; k < 3; ++k) out->mean_velocity[k] = g.A[k] / (double)g.nf;
+    out->tile_k = h->K;
+    out->species_per_block = h->gsz;
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, double* Xads) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (geom < 0 || geom >= h->ngeom) return fail(LBMP_EINVAL, "geometry index out of range");
+    GeomHost& g = h->g[geom];
+    if (species < 0 || species >= g.S) return fail(LBMP_EINVAL, "species index out of range");
+    const int64_t N = g.N, NI = g.NI, NIa = std::max<int64_t>(NI, 1);
+    const int64_t t = h->steps + 1;
+    const size_t es = h->prec == LBMP_FP32 ? 4 : 8;
+    const char* base = static_cast<const char*>((t & 1) ? g.X1 : g.X0) + (size_t)species * 4 * N * es;
+    const char* abase = static_cast<const char*>(g.Xa) + (size_t)species * 4 * NIa * es;
+    std::vector<char> hx(4 * N * es), ha(4 * NIa * es);
+    std::vector<int8_t> cls(N);
+    std::vector<int32_t> ilist(NIa);
+    LBMP_HIP(hipMemcpyAsync(hx.data(), base, hx.size(), hipMemcpyDeviceToHost, h->stream));
+    LBMP_HIP(hipMemcpyAsync(ha.data(), abase, ha.size(), hipMemcpyDeviceToHost, h->stream));
+    LBMP_HIP(hipMemcpyAsync(cls.data(), g.flow->d.cls, N, hipMemcpyDeviceToHost, h->stream));
+    if (NI > 0) LBMP_HIP(hipMemcpyAsync(ilist.data(), g.flow->d.ilist, NI * 4, hipMemcpyDeviceToHost, h->stream));
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    auto at = [&](const std::vector<char>& v, size_t i) {
+        return es == 4 ? (double)reinterpret_cast<const float*>(v.data())[i]
+                       : reinterpret_cast<const double*>(v.data())[i];
+    };
+    const double rr = g.rho_ref[species], gr = g.gam_ref[species];
+    for (int q = 0; q < 4; ++q) {
+        const double cq = q == 0 ? 1.0 : g.V[3 * species + q - 1];
+        for (int64_t n = 0; n < N; ++n)
+            if (X) X[q * N + n] = cls[n] ? at(hx, q * N + n) + cq * rr : 0.0;
+        if (Xads) {
+            for (int64_t n = 0; n < N; ++n) Xads[q * N + n] = 0.0;
+            for (int64_t i = 0; i < NI; ++i) Xads[q * N + ilist[i]] = at(ha, q * NIa + i) + cq * gr;
+        }
+    }
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_profile_steps(lbmp_mp* h, int64_t n_steps, double* ms_step_kernel,
+                                        double* ms_total) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (n_steps < 1) return fail(LBMP_EINVAL, "n_steps must be >= 1");
+    if (h->steps + n_steps > h->tmax)
+        return fail(LBMP_ESTATE, "%lld steps would exceed max_steps_recorded = %lld",
+                    (long long)(h->steps + n_steps), (long long)h->tmax);
+    hipStream_t s = h->stream;
+    std::vector<hipEvent_t> ev(2 * n_steps + 2);
+    for (auto& e : ev) LBMP_HIP(hipEventCreate(&e));
+    LBMP_HIP(hipEventRecord(ev[2 * n_steps], s));
+    for (int64_t i = 0; i < n_steps; ++i) {
+        LBMP_HIP(hipEventRecord(ev[2 * i], s));
+        if (h->prec == LBMP_FP32) launch_step_kernel<float>(h, s); else launch_step_kernel<double>(h, s);
+        LBMP_HIP(hipEventRecord(ev[2 * i + 1], s));
+        if (h->prec == LBMP_FP32) launch_step_tail<float>(h, s); else launch_step_tail<double>(h, s);
+    }
+    LBMP_HIP(hipEventRecord(ev[2 * n_steps + 1], s));
+    LBMP_HIP(hipEventSynchronize(ev[2 * n_steps + 1]));
+    double ks = 0.0;
+    for (int64_t i = 0; i < n_steps; ++i) {
+        float ms = 0.f;
+        LBMP_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        ks += ms;
+    }
+    float tot = 0.f;
+    LBMP_HIP(hipEventElapsedTime(&tot, ev[2 * n_steps], ev[2 * n_steps + 1]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    h->steps += n_steps;
+    if (ms_step_kernel) *ms_step_kernel = ks;
+    if (ms_total) *ms_total = tot;
+    return LBMP_OK;
+}
+
+extern "C" void mp_free(lbmp_mp* h) {
+    if (!h || h->magic != MP_MAGIC) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->magic = 0;
+    delete h;
+}

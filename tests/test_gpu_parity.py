@@ -1,0 +1,165 @@
+"""GPU path vs the FP64 oracle, through the C-ABI (liblbmp.so).
+
+Tolerances: FP64 propagation must agree to rounding (1e-10 relative); FP32
+propagation with FP64 sums must satisfy
+|D_gpu - D_ref| <= 1e-5 * max(|D_ref|, 1e-3 D_b) at every recorded time
+(relative 1e-5, with a floor where D decays towards zero across a slit).
+Integer work (node classes, interface counts) must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_2470_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1303_2470_amd import lbmp
+    lbmp.load_library()
+    return lbmp
+
+
+def d_err(D, Dref, db):
+    return float(np.max(np.abs(D - Dref) / np.maximum(np.abs(Dref), 1e-3 * db)))
+
+
+# ---------------------------------------------------------------- geometry
+@pytest.mark.parametrize("shape,frac,seed,nb", [((13, 11, 9), 0.3, 1, 18), ((7, 5, 33), 0.25, 2, 6),
+                                                ((64, 3, 2), 0.4, 3, 18), ((300, 1, 1), 0.3, 4, 18)])
+def test_classes_match_oracle(lb, shape, frac, seed, nb):
+    nx, ny, nz = shape
+    m = inputs.random_mask(nx, ny, nz, frac, seed)
+    fl = lb.lb_flow_from_velocity(m, np.zeros((3,) + m.shape), iface_nbhd=nb)
+    cls, nf, ni = fl.classes()
+    ref = oracle.classify(m, nbhd=nb)
+    assert np.array_equal(cls, ref)
+    assert nf == int((ref > 0).sum()) and ni == int((ref == 2).sum())
+
+
+# ---------------------------------------------------------------- fluid
+def test_bgk_matches_oracle_porous(lb):
+    m = inputs.random_mask(12, 10, 9, 0.25, seed=7)
+    g = [4e-6, -1e-6, 2e-6]
+    ref = oracle.bgk(m, 0.8, g, 1e-9, 20000, check_every=50)
+    fl = lb.lb_flow_solve(m, 0.8, g, 1e-9, 20000, check_every=50)
+    u = fl.velocity()
+    assert ref["converged"] and fl.converged
+    assert abs(fl.steps - ref["steps"]) <= 50
+    assert np.abs(u - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
+
+
+def test_bgk_fixed_steps_bitwise_close(lb):
+    """Same number of steps (no convergence stop): FP64 agreement to rounding."""
+    m = inputs.random_mask(9, 8, 7, 0.2, seed=8)
+    g = [1e-5, 0, 0]
+    ref = oracle.bgk(m, 1.0, g, 0.0, 300, check_every=100)
+    fl = lb.lb_flow_solve(m, 1.0, g, 0.0, 300, check_every=100, allow_unconverged=True)
+    assert fl.steps == ref["steps"] == 300
+    assert np.abs(fl.velocity() - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
+
+
+def test_bgk_slit_full_size_equals_column(lb):
+    """64x64x66 Poiseuille slit at Pe = 10 vs the oracle's laterally reduced column."""
+    L, db = 64, 0.01
+    g = inputs.poiseuille_force(10.0, db, L)
+    fl = lb.lb_flow_solve(inputs.slit_mask(64, 64, L + 2), 1.0, [g, 0, 0], 1e-10, 200000)
+    ref = oracle.bgk(inputs.slit_mask(1, 1, L + 2), 1.0, [g, 0, 0], 1e-10, 200000)
+    u = fl.velocity()
+    assert fl.steps == ref["steps"]
+    assert np.abs(u[0] - ref["u"][0, :, :1, :1]).max() <= 1e-10 * ref["u"][0].max()
+    assert np.abs(u[1:]).max() < 1e-14
+
+
+# ---------------------------------------------------------------- propagation
+def run_gpu(lb, flow, sp, prec, T):
+    mp = lb.mp_init(flow, sp, prec, T)
+    lb.mp_step_n(mp, T)
+    out = lb.mp_vacf(mp, 0, 0, T + 1)
+    mp.free()
+    return out
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_slit_c1_full_length(lb, prec):
+    """4x4x24 slit, Delta = 0.5, k_a = k_d = 0.01, 20000 steps (FP64 and FP32)."""
+    m = inputs.slit_mask(4, 4, 24)
+    T = 20000
+    lam = oracle.lambda_from(delta=0.5)
+    db = lam / 12
+    ref = oracle.vacf(m, None, lam, 0.01, 0.01, T)
+    Dref = oracle.d_of_t(ref["Z"], ref["V"])
+    flow = lb.lb_flow_from_velocity(m, np.zeros((3,) + m.shape))
+    out = run_gpu(lb, flow, {"Delta": 0.5, "k_a": [0.01], "k_d": [0.01]}, prec, T)
+    D = out["D"][0]
+    tol = 1e-10 if prec == 64 else 1e-5
+    assert d_err(D, Dref, db) < tol
+    # lattice closed form for the direction along the walls
+    assert np.abs(D[0] / db - (20 + 2 * 5 / 6) / 24).max() < (1e-12 if prec == 64 else 1e-6)
+    assert abs(out["mass"].sum() - 1) < (1e-13 if prec == 64 else 1e-6)
+    fa = out["mass"][0, 1] / out["mass"][0].sum()
+    assert abs(fa - 1 / 12) < (1e-12 if prec == 64 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_random_porous_random_flow(lb, prec):
+    """Random mask (ragged tiles), random velocity, three species, 600 steps."""
+    m = inputs.random_mask(13, 11, 9, 0.3, seed=5)
+    u = inputs.random_velocity(m, 0.03, seed=6)
+    lam = 0.9
+    ka = np.array([0.0, 0.05, 0.2])
+    kd = np.array([0.3, 0.02, 0.5])
+    T = 600
+    flow = lb.lb_flow_from_velocity(m, u)
+    out = run_gpu(lb, flow, {"D_b": lam / 12, "k_a": ka, "k_d": kd}, prec, T)
+    for s in range(3):
+        ref = oracle.vacf(m, u, lam, ka[s], kd[s], T)
+        Dref = oracle.d_of_t(ref["Z"], ref["V"])
+        assert d_err(out["D"][s], Dref, lam / 12) < (1e-10 if prec == 64 else 1e-5)
+        zs = np.abs(ref["Z"]).max()
+        assert np.abs(out["Z"][s] - ref["Z"]).max() < (1e-12 if prec == 64 else 1e-6) * zs
+        assert np.allclose(out["vbar"][s], ref["V"], rtol=1e-6 if prec == 32 else 1e-12, atol=1e-15)
+        mref = ref["mass"][:, -1]
+        assert np.allclose(out["mass"][s], mref, rtol=1e-5 if prec == 32 else 1e-12)
+
+
+def test_state_matches_oracle_fields(lb):
+    """Node-by-node fields after 50 steps (FP64), density and x-moment."""
+    m = inputs.random_mask(9, 7, 6, 0.3, seed=12)
+    u = inputs.random_velocity(m, 0.02, seed=13)
+    lam, pa, pd = 1.0, 0.1, 0.05
+    flow = lb.lb_flow_from_velocity(m, u)
+    mp = lb.mp_init(flow, {"D_b": lam / 12, "k_a": [pa], "k_d": [pd]}, 64, 50)
+    lb.mp_step_n(mp, 50)
+    X, Xa = lb.mp_state(mp, 0, 0)
+    cls = oracle.classify(m)
+    Zp = (cls > 0).sum() + (cls == 2).sum() * pa / pd
+    rho = np.where(cls > 0, 1 / Zp, 0.0)
+    gam = np.where(cls == 2, pa / pd / Zp, 0.0)
+    r1, g1 = oracle.propagate(m, u, lam, pa, pd, 51, rho, gam)
+    assert np.abs(X[0] - r1).max() < 1e-14
+    assert np.abs(Xa[0] - g1).max() < 1e-14
+    mp.free()
+
+
+@pytest.mark.parametrize("pe", [10.0, 100.0])
+def test_poiseuille_c2_full_length_fp32(lb, pe):
+    """64x64x66 slit, BGK flow at Pe, 1e5 FP32 steps, k_a = 5e-3, k_d = 2e-3,
+    against the oracle's laterally reduced column (flow and propagation)."""
+    L, db, ka, kd = 64, 0.01, 0.005, 0.002
+    T = 100000
+    g = inputs.poiseuille_force(pe, db, L)
+    fl = lb.lb_flow_solve(inputs.slit_mask(64, 64, L + 2), 1.0, [g, 0, 0], 1e-10, 200000)
+    out = run_gpu(lb, fl, {"D_b": db, "k_a": [ka], "k_d": [kd]}, 32, T)
+    col = inputs.slit_mask(1, 1, L + 2)
+    rf = oracle.bgk(col, 1.0, [g, 0, 0], 1e-10, 200000)
+    ref = oracle.vacf(col, rf["u"], 12 * db, ka, kd, T, qmask=2 | 8)
+    Dref = oracle.d_of_t(ref["Z"], ref["V"])
+    D = out["D"][0]
+    for gdir in (0, 2):
+        assert d_err(D[gdir], Dref[gdir], db) < 1e-5, gdir
