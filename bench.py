@@ -97,8 +97,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer 5 times (known traffic, to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the batched workload is one GPU's share "
@@ -110,6 +112,15 @@ def main():
     from paper_1303_2470_amd import inputs, lbmp
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 5}))
+        return
     lbmp.load_library()
     flows, species, nf, ni = build_workload(lbmp, inputs)
     total = args.warmup + args.steps
@@ -157,10 +168,11 @@ def main():
                    "fluid_nodes": int(sum(nf)), "interface_nodes": int(sum(ni)),
                    "lattice_nodes": int(lat_nodes),
                    "lattice_node_species_updates_per_s": lat_nodes * N_SPECIES * args.steps / (tot_ms / 1e3),
-                   "tile": {"K": st["tile_k"], "species_per_block": st["species_per_block"]}},
+                   "tile": {"K": st["tile_k"], "species_per_block": st["species_per_block"],
+                            "variant": "lds-box" if st["kernel_variant"] == 1 else "direct"}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_mp_step", "kernel_avg_ms": k_avg_s * 1e3,
+                     "kernel": "k_mp_step_box" if st["kernel_variant"] == 1 else "k_mp_step", "kernel_avg_ms": k_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg},
         "mass_error_max": mass_err,
     }

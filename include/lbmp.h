@@ -165,6 +165,7 @@ typedef struct {
     double mean_velocity[3];
     int tile_k;            /* z-planes per thread chosen by the tile tuner */
     int species_per_block; /* species per block chosen by the tile tuner */
+    int kernel_variant;    /* 0: direct neighbour loads, 1: fields staged through LDS */
 } lbmp_stats;
 /* Set-up statistics of geometry `geom`. */
 lbmp_status mp_stats(const lbmp_mp* h, int geom, lbmp_stats* st);
@@ -183,6 +184,48 @@ lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, double* Xads)
 lbmp_status mp_profile_steps(lbmp_mp* h, int64_t n_steps, double* ms_step_kernel, double* ms_total);
 /* Synchronises the handle's stream and releases the handle. */
 void mp_free(lbmp_mp* h);
+
+/* ------------------------------------------------------------------ surrogate
+ * A learned shortcut for the paper's first stated use (Sec. IV: predicting
+ * D(t) for species of known k_a, k_d in a given medium, and the converse
+ * extraction of k_a, k_d from D(t)): a network mapping the six features
+ * (porosity, specific surface N_I/N, Peclet number, log10 k_a, log10 k_d,
+ * log10 t) to log10(D_x(t)/D_b), trained on runs of the method above and
+ * judged against it. Layers 6 -> 256 -> 256 -> 256 -> 1 with SiLU; BF16
+ * matrix-core products with FP32 accumulation, FP32 master weights, Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8), loss mean((f(x) - y)^2) on z-scored
+ * inputs and target. All compute on the device; device pointers below are
+ * FP32 arrays: x [n][6], y [n], idx [B] (int32 row indices).
+ */
+typedef struct lbmp_sg lbmp_sg;
+/* Number of trainable parameters (133,633). */
+lbmp_status sg_param_count(int64_t* n);
+/* Workspace for a network trained with batches up to batch_max (a multiple of 32). */
+lbmp_status sg_workspace_bytes(int batch_max, size_t* bytes);
+/* New network; weights and biases U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a
+ * splitmix64 stream seeded with `seed`; identity normalisation. */
+lbmp_status sg_create(int batch_max, uint64_t seed, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                      lbmp_sg** out);
+/* Host parameter vector (FP32), layer by layer: W [out][in] row-major then b [out]. */
+lbmp_status sg_set_params(lbmp_sg* h, const float* params);
+lbmp_status sg_get_params(lbmp_sg* h, float* params);
+/* Input z-scoring (x - mean)/std per feature, target (y - y_mean)/y_std. */
+lbmp_status sg_set_normalization(lbmp_sg* h, const float* x_mean, const float* x_std, float y_mean,
+                                 float y_std);
+/* One Adam step on rows idx_dev[0..B-1] of (x_dev, y_dev) (idx_dev NULL: the
+ * first B rows); B a multiple of 32 up to batch_max. Asynchronous unless
+ * loss_host is given (then the batch loss, in normalised units, is returned). */
+lbmp_status sg_train_step(lbmp_sg* h, const float* x_dev, const float* y_dev, const int32_t* idx_dev,
+                          int B, float lr, float* loss_host);
+/* Loss and parameter gradients (host, packed like the parameters) on the
+ * first B rows, without updating. Synchronous. */
+lbmp_status sg_gradients(lbmp_sg* h, const float* x_dev, const float* y_dev, int B, float* grads_host,
+                         float* loss_host);
+/* Predictions y_dev[i] = network(x_dev[i]) in target units, i < n. Asynchronous. */
+lbmp_status sg_predict(lbmp_sg* h, const float* x_dev, int64_t n, float* y_dev);
+/* Waits for the handle's stream. */
+lbmp_status sg_sync(lbmp_sg* h);
+void sg_free(lbmp_sg* h);
 
 #ifdef __cplusplus
 }

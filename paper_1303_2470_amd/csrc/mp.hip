@@ -25,6 +25,7 @@
 // and ping-pong parity live in device memory, so a captured graph of steps
 // can be replayed.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -42,6 +43,7 @@ struct GeomDev {
     int nx, ny, nz, S;
     int64_t N, NI;
     int pb, zb, ngrp;          // plane blocks, z blocks, species groups
+    int64_t ntile;             // tiles of the launched kernel variant
     int64_t blk0;              // first logical block of this geometry
     const int8_t* cls;
     const int32_t* slot;
@@ -122,6 +124,19 @@ __device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, int off
 }
 __device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+    using v2u = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, off, soff, 0);
 }
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
@@ -232,7 +247,7 @@ __global__ void __launch_bounds__(BLK) k_mp_step(const GeomDev<T>* __restrict__ 
     const T* Xin = (t & 1) ? G.X1 : G.X0;
     T* Xout = (t & 1) ? G.X0 : G.X1;
     const int s_begin = grp * gsz, s_end = min(G.S, s_begin + gsz);
-    const int64_t ntile = (int64_t)G.pb * G.zb;
+    const int64_t ntile = G.ntile;
     const int64_t NI = G.NI;
 
     for (int s = s_begin; s < s_end; ++s) {
@@ -303,6 +318,348 @@ __global__ void __launch_bounds__(BLK) k_mp_step(const GeomDev<T>* __restrict__ 
     }
 }
 
+// The same step with each field staged through LDS. A block owns a tile of
+// TX x TY lattice columns and K consecutive z-planes; for every field (species,
+// quantity) the block loads the tile plus a one-node periodic halo, a box of
+// (K+2) x (TY+2) x (TX+2) values, into one of two LDS buffers while it updates
+// the previous field from the other buffer. Link data stay in registers for
+// all the fields of the block.
+constexpr int TX = 64, TY = BLK / TX;
+
+template <int K>
+struct Box {
+    static constexpr int PX = TX + 2, PY = TY + 2, PL = PX * PY, N = PL * (K + 2);
+    static constexpr int LOADS = (N + BLK - 1) / BLK;
+};
+
+template <typename T, int K>
+__global__ void __launch_bounds__(BLK) k_mp_step_box(const GeomDev<T>* __restrict__ geoms, int ngeom,
+                                                     int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
+    using B = Box<K>;
+    __shared__ T box[2][B::LOADS * BLK];
+    __shared__ double lds[NRED * BLK];
+    constexpr int E = (int)sizeof(T);
+    T* const tag = nullptr;
+    double* const dtag = nullptr;
+    const int64_t lb = xcd_remap(blockIdx.x, nblocks);
+    const int gi = find_geom(geoms, ngeom, lb);
+    const GeomDev<T>& G = geoms[gi];
+    const int64_t local = lb - G.blk0;
+    const int grp = (int)(local % G.ngrp);
+    const int64_t tile = local / G.ngrp;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int txi = (int)(tile % ntx), tyi = (int)((tile / ntx) % nty), zbi = (int)(tile / ((int64_t)ntx * nty));
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = zbi * K;
+    const int N = (int)G.N, plane = nx * ny;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inplane = x < nx && y < ny;
+    // global offsets of this thread's share of the box (same for every field)
+    int goff[B::LOADS];
+#pragma unroll
+    for (int i = 0; i < B::LOADS; ++i) {
+        const int e = tid + i * BLK;
+        if (e < B::N) {
+            const int j = e / B::PL, r = e % B::PL, yy = r / B::PX, xx = r % B::PX;
+            const int gx = modp(x0 - 1 + xx, nx), gy = modp(y0 - 1 + yy, ny), gz = modp(z0 - 1 + j, nz);
+            goff[i] = (gz * plane + gy * nx + gx) * E;
+        } else {
+            goff[i] = OOB;
+        }
+    }
+    const int64_t t = ctl->t;
+    bool act[K], isI[K];
+    int offn[K], offa[K];
+    double pin[K][NL], sig[K], src[K], av[K][3];
+    uint32_t rbase[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int n = modp(z0 + j, nz) * plane + (inplane ? y * nx + x : 0);
+        act[j] = inplane && (z0 + j < nz) && G.cls[n] != 0;
+        const int sl = act[j] ? G.slot[n] : -1;
+        isI[j] = sl >= 0;
+        offn[j] = act[j] ? n * E : OOB;
+        offa[j] = isI[j] ? sl * E : OOB;
+        const int offn8 = act[j] ? n * 8 : OOB;
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            pin[j][k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * E), offn[j]);
+        sig[j] = bload(dtag, mkrsrc(G.sig, (int64_t)N * 8), offn8);
+        src[j] = (double)bload(tag, mkrsrc(G.src, (int64_t)N * E), offn[j]);
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            av[j][g] = (double)bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * E), offn[j]);
+        rbase[j] = hash32((uint32_t)n * 0x9e3779b9u ^ hash32((uint32_t)t ^ ((uint32_t)gi << 24)));
+    }
+    const T* Xin = (t & 1) ? G.X1 : G.X0;
+    T* Xout = (t & 1) ? G.X0 : G.X1;
+    const int s_begin = grp * gsz, s_end = min(G.S, s_begin + gsz);
+    const int nf = 4 * (s_end - s_begin);
+    const int64_t ntile = G.ntile;
+    const int64_t NI = G.NI;
+
+    // prologue: field 0 into buffer 0
+    T pre[B::LOADS];
+    {
+        const auto r0 = mkrsrc(Xin + (int64_t)(4 * s_begin) * N, (int64_t)N * E);
+#pragma unroll
+        for (int i = 0; i < B::LOADS; ++i) pre[i] = bload(tag, r0, goff[i]);
+#pragma unroll
+        for (int i = 0; i < B::LOADS; ++i) box[0][tid + i * BLK] = pre[i];
+    }
+    __syncthreads();
+
+    double red[NRED];
+    uint32_t rs[K];
+    double pa = 0.0, pd = 0.0;
+    for (int fi = 0; fi < nf; ++fi) {
+        const int s = s_begin + fi / 4, q = fi % 4;
+        const int64_t f = 4 * s + q;
+        if (q == 0) {
+            pa = (double)G.prob[2 * s];
+            pd = (double)G.prob[2 * s + 1];
+#pragma unroll
+            for (int j = 0; j < K; ++j) rs[j] = hash32(rbase[j] ^ ((uint32_t)s * 0x632be5abu)) | 1u;
+#pragma unroll
+            for (int k = 0; k < NRED; ++k) red[k] = 0.0;
+        }
+        // prefetch the next field
+        if (fi + 1 < nf) {
+            const auto rn = mkrsrc(Xin + (f + 1) * N, (int64_t)N * E);
+#pragma unroll
+            for (int i = 0; i < B::LOADS; ++i) pre[i] = bload(tag, rn, goff[i]);
+        }
+        const auto rout = mkrsrc(Xout + f * N, (int64_t)N * E);
+        const auto rads = mkrsrc(G.Xa + f * NI, NI * E);
+        double xa[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) xa[j] = (double)bload(tag, rads, offa[j]);
+        const double cq = (double)G.coef[f];
+        const T* bx = box[fi & 1];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            // centre of node j in the box: plane j+1, row ly+1, column lx+1
+            const int c0 = (j + 1) * B::PL + (ly + 1) * B::PX + (lx + 1);
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int o = -lcz(k) * B::PL - lcy(k) * B::PX - lcx(k);
+                acc = __builtin_fma((double)bx[c0 + o], pin[j][k], acc);
+            }
+            const double xc = (double)bx[c0];
+            const double fa = isI[j] ? pa * xc : 0.0;
+            const double fd = pd * xa[j];
+            double nv = __builtin_fma(-xc, sig[j], xc);
+            nv = __builtin_fma(cq, src[j], (nv - fa) + fd) + acc;
+            const uint32_t r1 = xorshift32(rs[j]);
+            bstore(store_round<T>(nv, r1), rout, offn[j]);
+            bstore(store_round<T>((xa[j] + fa) - fd, (r1 >> 3) | (r1 << 29)), rads, offa[j]);
+            const double xd = act[j] ? xc : 0.0;
+            if (q == 0) {
+                red[3] += xd;
+                red[7] += xa[j];
+            } else {
+                red[q - 1] = __builtin_fma(xd, av[j][q - 1], red[q - 1]);
+                red[3 + q] += xd + xa[j];
+            }
+        }
+        if (fi + 1 < nf) {
+#pragma unroll
+            for (int i = 0; i < B::LOADS; ++i) box[(fi + 1) & 1][tid + i * BLK] = pre[i];
+        }
+        if (q == 3) {
+            double r;
+            block_sum8(red, lds, r);   // synchronises the block
+            if (tid < NRED) G.part[((int64_t)s * ntile + tile) * NRED + tid] = r;
+        } else {
+            __syncthreads();
+        }
+    }
+}
+
+// The step as a z-march. A block owns a tile of TX x TY lattice columns, a
+// segment of consecutive z-planes and a group of G species (F = 4G fields).
+// It keeps, for every field, the planes z-1, z, z+1 of the tile plus a
+// one-node periodic halo in an LDS ring; plane z+2 is fetched from global
+// memory while plane z is updated. Each field value is thus read from global
+// memory once per step (plus the halo), the link data of a node once for all
+// F fields, and the FP64 sums are reduced across the block once per species.
+template <int F>
+struct Ring {
+    static constexpr int PX = TX + 2, PY = TY + 2, PL = PX * PY;  // one haloed plane
+    static constexpr int LOADS = (PL + BLK - 1) / BLK;
+};
+
+template <typename T, int G>
+__global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__ geoms, int ngeom,
+                                                  int64_t nblocks, int zseg, const Ctl* __restrict__ ctl) {
+    constexpr int F = 4 * G;
+    using R = Ring<F>;
+    static_assert(NRED * BLK * sizeof(double) <= 3 * F * R::PL * sizeof(T) + 4096,
+                  "reduction scratch must fit in the plane ring");
+    __shared__ __align__(16) char smem[3 * F * R::PL * sizeof(T) > NRED * BLK * sizeof(double)
+                                           ? 3 * F * R::PL * sizeof(T) : NRED * BLK * sizeof(double)];
+    T* ring = reinterpret_cast<T*>(smem);  // [3][F][PL]
+    constexpr int E = (int)sizeof(T);
+    T* const tag = nullptr;
+    double* const dtag = nullptr;
+    const int64_t lb = xcd_remap(blockIdx.x, nblocks);
+    const int gi = find_geom(geoms, ngeom, lb);
+    const GeomDev<T>& Gm = geoms[gi];
+    const int64_t local = lb - Gm.blk0;
+    const int grp = (int)(local % Gm.ngrp);
+    const int64_t tile = local / Gm.ngrp;
+    const int nx = Gm.nx, ny = Gm.ny, nz = Gm.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int txi = (int)(tile % ntx), tyi = (int)((tile / ntx) % nty), zsi = (int)(tile / ((int64_t)ntx * nty));
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int zs = zsi * zseg, ze = min(nz, zs + zseg);
+    const int N = (int)Gm.N, plane = nx * ny;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inplane = x < nx && y < ny;
+    const int c0 = (ly + 1) * R::PX + (lx + 1);  // this thread's column in a haloed plane
+    const int own = inplane ? y * nx + x : 0;
+    // this thread's share of a haloed plane: in-plane offsets (wrapped)
+    int poff[R::LOADS];
+#pragma unroll
+    for (int i = 0; i < R::LOADS; ++i) {
+        const int e = tid + i * BLK;
+        if (e < R::PL) {
+            const int yy = e / R::PX, xx = e % R::PX;
+            poff[i] = modp(y0 - 1 + yy, ny) * nx + modp(x0 - 1 + xx, nx);
+        } else {
+            poff[i] = -1;
+        }
+    }
+    const int64_t t = ctl->t;
+    const T* Xin = (t & 1) ? Gm.X1 : Gm.X0;
+    T* Xout = (t & 1) ? Gm.X0 : Gm.X1;
+    const int s0 = grp * G, ns = min(G, Gm.S - s0);
+    const int64_t NI = Gm.NI;
+    const uint32_t tseed = hash32((uint32_t)t ^ ((uint32_t)gi << 24));
+
+    // plane pz of every field of the group -> registers
+    // one resource per array: the group's fields of X, the group's adsorbed
+    // fields, the link table; the field (or link) index goes to the scalar offset
+    const auto rin = mkrsrc(Xin + (int64_t)(4 * s0) * N, (int64_t)(4 * ns) * N * E);
+    const auto rout = mkrsrc(Xout + (int64_t)(4 * s0) * N, (int64_t)(4 * ns) * N * E);
+    const auto rads = mkrsrc(Gm.Xa + (int64_t)(4 * s0) * NI, (int64_t)(4 * ns) * NI * E);
+    const auto rpin = mkrsrc(Gm.pin, (int64_t)NL * N * E);
+    const auto ra = mkrsrc(Gm.a, (int64_t)3 * N * E);
+    auto fetch = [&](int pz, T (&reg)[F][R::LOADS]) {
+        const int zo = modp(pz, nz) * plane;
+        int vo[R::LOADS];
+#pragma unroll
+        for (int i = 0; i < R::LOADS; ++i) vo[i] = poff[i] >= 0 ? (zo + poff[i]) * E : OOB;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int i = 0; i < R::LOADS; ++i)
+                reg[f][i] = f < 4 * ns ? bload(tag, rin, vo[i], f * N * E) : T(0);
+    };
+    auto stash = [&](int slot, const T (&reg)[F][R::LOADS]) {
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int i = 0; i < R::LOADS; ++i) {
+                const int e = tid + i * BLK;
+                if (e < R::PL) ring[(slot * F + f) * R::PL + e] = reg[f][i];
+            }
+    };
+    T pre[F][R::LOADS];
+    fetch(zs - 1, pre);
+    stash(0, pre);
+    fetch(zs, pre);
+    stash(1, pre);
+    fetch(zs + 1, pre);
+    stash(2, pre);
+    __syncthreads();
+
+    double red[G][NRED];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) red[g][k] = 0.0;
+
+    for (int z = zs; z < ze; ++z) {
+        const int sm = (z - zs) % 3, sc = (z - zs + 1) % 3, sp = (z - zs + 2) % 3;
+        // link data of this thread's node (x, y, z)
+        const int n = z * plane + own;
+        const bool act = inplane && Gm.cls[n] != 0;
+        const int sl = act ? Gm.slot[n] : -1;
+        const bool isI = sl >= 0;
+        const int offn = act ? n * E : OOB, offa = isI ? sl * E : OOB;
+        double pin[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, rpin, offn, k * N * E);
+        const double sig = bload(dtag, mkrsrc(Gm.sig, (int64_t)N * 8), act ? n * 8 : OOB);
+        const double src = (double)bload(tag, mkrsrc(Gm.src, (int64_t)N * E), offn);
+        double av[3];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) av[g] = (double)bload(tag, ra, offn, g * N * E);
+        // plane z+2 in flight while plane z is updated
+        const bool more = z + 1 < ze;
+        if (more) fetch(z + 2, pre);
+        const uint32_t rnode = hash32((uint32_t)n * 0x9e3779b9u ^ tseed);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g >= ns) break;
+            const int s = s0 + g;
+            const double pa = (double)Gm.prob[2 * s], pd = (double)Gm.prob[2 * s + 1];
+            uint32_t rs = hash32(rnode ^ ((uint32_t)s * 0x632be5abu)) | 1u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = 4 * g + q;
+                const int64_t fg = 4 * s + q;
+                const double xa = (double)bload(tag, rads, offa, f * (int)NI * E);
+                const T* pm = ring + (sm * F + f) * R::PL;
+                const T* pc = ring + (sc * F + f) * R::PL;
+                const T* pp = ring + (sp * F + f) * R::PL;
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {
+                    const int o = c0 - lcy(k) * R::PX - lcx(k);
+                    const T v = lcz(k) > 0 ? pm[o] : (lcz(k) < 0 ? pp[o] : pc[o]);
+                    acc = __builtin_fma((double)v, pin[k], acc);
+                }
+                const double xc = (double)pc[c0];
+                const double fa = isI ? pa * xc : 0.0;
+                const double fd = pd * xa;
+                double nv = __builtin_fma(-xc, sig, xc);
+                nv = __builtin_fma((double)Gm.coef[fg], src, (nv - fa) + fd) + acc;
+                const uint32_t r1 = xorshift32(rs);
+                bstore(store_round<T>(nv, r1), rout, offn, f * N * E);
+                bstore(store_round<T>((xa + fa) - fd, (r1 >> 3) | (r1 << 29)), rads, offa, f * (int)NI * E);
+                const double xd = act ? xc : 0.0;
+                if (q == 0) {
+                    red[g][3] += xd;
+                    red[g][7] += xa;
+                } else {
+                    red[g][q - 1] = __builtin_fma(xd, av[q - 1], red[g][q - 1]);
+                    red[g][3 + q] += xd + xa;
+                }
+            }
+        }
+        __syncthreads();          // every read of plane z-1 is done
+        if (more) stash(sm, pre); // plane z+2 takes its slot
+        __syncthreads();
+    }
+    // the ring is free: reuse it for the block sums
+    double* lds = reinterpret_cast<double*>(smem);
+    const int64_t ntile = Gm.ntile;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (g >= ns) break;
+        double r;
+        block_sum8(red[g], lds, r);
+        if (tid < NRED) Gm.part[((int64_t)(s0 + g) * ntile + tile) * NRED + tid] = r;
+    }
+}
+
 // Sum the block partials of every (geometry, species) into the series at the
 // current time, in a fixed order; then advance the state time.
 template <typename T>
@@ -314,7 +671,7 @@ __global__ void k_mp_reduce(const GeomDev<T>* __restrict__ geoms, int ngeom,
     if (w < nwork) {
         const int gi = work[2 * w], s = work[2 * w + 1];
         const GeomDev<T>& G = geoms[gi];
-        const int64_t ntile = (int64_t)G.pb * G.zb;
+        const int64_t ntile = G.ntile;
         const double* P = G.part + (int64_t)s * ntile * NRED;
         double acc[NRED];
 #pragma unroll
@@ -510,7 +867,7 @@ struct TuneKey {
     bool operator<(const TuneKey& o) const { return std::tie(prec, shape) < std::tie(o.prec, o.shape); }
 };
 struct TuneVal {
-    int K, gsz;
+    int K, gsz, variant;
 };
 static std::map<TuneKey, TuneVal> g_tune_cache;
 
@@ -542,7 +899,7 @@ struct lbmp_mp {
     int32_t* work;
     int nwork;
     double* setup_tmp;
-    int K, gsz;
+    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box
     int64_t nblocks;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -553,10 +910,10 @@ namespace {
 
 constexpr int GRAPH_CHUNK = 64;
 
-int64_t ntile_for(const lbmp_flow* f, int K) {
-    int64_t pb = ((int64_t)f->nx * f->ny + BLK - 1) / BLK;
-    int64_t zb = (f->nz + K - 1) / K;
-    return pb * zb;
+int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
+    const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
+    if (variant >= 1) return (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * zb;
+    return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
 
 int64_t setup_doubles(int64_t N) { return 22 * N + ((N + BLK - 1) / BLK) * SETUP_RED + SETUP_RED; }
@@ -643,7 +1000,7 @@ lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species,
         g.N = g.flow->N;
         g.NI = g.flow->ni;
         g.nf = g.flow->nf;
-        g.ntile_max = ntile_for(g.flow, 1);
+        g.ntile_max = std::max(ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1));
     }
     return h;
 }
@@ -652,6 +1009,19 @@ template <typename T>
 void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     dim3 grid((unsigned)h->nblocks);
+    if (h->variant == 2) {
+        switch (h->gsz) {
+            case 1: k_mp_march<T, 1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->nblocks, h->K, h->ctl); break;
+            case 2: k_mp_march<T, 2><<<grid, BLK, 0, s>>>(G, h->ngeom, h->nblocks, h->K, h->ctl); break;
+            default: k_mp_march<T, 4><<<grid, BLK, 0, s>>>(G, h->ngeom, h->nblocks, h->K, h->ctl); break;
+        }
+        return;
+    }
+    if (h->variant == 1) {
+        if (h->K == 1) k_mp_step_box<T, 1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+        else k_mp_step_box<T, 2><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+        return;
+    }
     switch (h->K) {
         case 1: k_mp_step<T, 1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl); break;
         default: k_mp_step<T, 2><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl); break;
@@ -691,8 +1061,9 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.pb = (int)(((int64_t)f->nx * f->ny + BLK - 1) / BLK);
         d.zb = (f->nz + h->K - 1) / h->K;
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
+        d.ntile = ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += (int64_t)d.pb * d.zb * d.ngrp;
+        blk += d.ntile * d.ngrp;
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -707,6 +1078,17 @@ lbmp_status upload_geoms(lbmp_mp* h) {
 
 lbmp_status upload(lbmp_mp* h) { return h->prec == LBMP_FP32 ? upload_geoms<float>(h) : upload_geoms<double>(h); }
 
+// The z-march kernel addresses a group's fields and the link table through
+// one 32-bit buffer range each.
+bool march_fits(const lbmp_mp* h, int G) {
+    const int64_t es = h->prec == LBMP_FP32 ? 4 : 8;
+    for (const auto& g : h->g) {
+        const int64_t big = std::max<int64_t>((int64_t)4 * std::min(G, g.S) * g.N, (int64_t)NL * g.N) * es;
+        if (big >= (int64_t)INT32_MAX - 64) return false;
+    }
+    return true;
+}
+
 // Pick (K, species per block) by timing a few steps of each candidate on the
 // set-up tables before the state exists. Results are cached per
 // (precision, shapes) for the life of the process.
@@ -719,31 +1101,56 @@ lbmp_status autotune(lbmp_mp* h) {
         work += g.nf * g.S;
         maxS = std::max(maxS, g.S);
     }
+    // LBMP_TILE="variant,K,species_per_block" pins the choice (tests, experiments)
+    if (const char* env = getenv("LBMP_TILE")) {
+        int v = 0, K = 1, gs = 1;
+        const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
+        const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
+        const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
+        if (nread == 3 && (ok01 || ok2)) {
+            h->variant = v;
+            h->K = K;
+            h->gsz = v == 2 ? gs : std::min(gs, std::max(1, maxS));
+            return upload(h);
+        }
+        return fail(LBMP_EINVAL, "LBMP_TILE must be 'variant,K,species_per_block': variant 0|1 with K 1|2, "
+                                 "or variant 2 with K = z-segment and 1|2|4 species per block");
+    }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
         h->K = it->second.K;
         h->gsz = it->second.gsz;
+        h->variant = it->second.variant;
         return upload(h);
     }
     if (work < (1 << 16)) {  // launch-bound sizes: one block per tile, all species
         h->K = 1;
         h->gsz = maxS;
-        g_tune_cache[key] = {h->K, h->gsz};
+        h->variant = 0;
+        g_tune_cache[key] = {h->K, h->gsz, h->variant};
         return upload(h);
     }
-    std::vector<std::pair<int, int>> cand;
-    for (int K : {1, 2})
-        for (int gs : {1, 2, 4, 8, 16, 32, 64})
-            if (gs <= maxS || gs == 1) cand.push_back({K, gs});
+    std::vector<TuneVal> cand;
+    for (int v : {0, 1})
+        for (int K : {1, 2})
+            for (int gs : {1, 2, 4, 8, 16, 32, 64})
+                if (gs <= maxS || gs == 1) cand.push_back({K, gs, v});
+    int maxz = 0;
+    for (auto& g : h->g) maxz = std::max(maxz, g.flow->nz);
+    for (int zs : {8, 16, 32, 64})
+        for (int gs : {1, 2, 4})
+            if ((gs <= maxS || gs == 1) && zs <= std::max(8, maxz) && march_fits(h, gs))
+                cand.push_back({zs, gs, 2});
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
     LBMP_HIP(hipEventCreate(&e1));
     float best = INFINITY;
-    TuneVal bv{2, 8};
+    TuneVal bv{2, 8, 0};
     const int reps = 3;
-    for (auto [K, gs] : cand) {
-        h->K = K;
-        h->gsz = gs;
+    for (auto c : cand) {
+        h->K = c.K;
+        h->gsz = c.gsz;
+        h->variant = c.variant;
         lbmp_status st = upload(h);
         if (st != LBMP_OK) return st;
         do_steps(h, 1, h->stream);
@@ -755,13 +1162,14 @@ lbmp_status autotune(lbmp_mp* h) {
         LBMP_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best) {
             best = ms;
-            bv = {K, gs};
+            bv = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->K = bv.K;
     h->gsz = bv.gsz;
+    h->variant = bv.variant;
     g_tune_cache[key] = bv;
     return upload(h);
 }
@@ -1057,6 +1465,7 @@ extern "C" lbmp_status mp_stats(const lbmp_mp* h, int geom, lbmp_stats* out) {
     for (int k = 0; k < 3; ++k) out->mean_velocity[k] = g.A[k] / (double)g.nf;
     out->tile_k = h->K;
     out->species_per_block = h->gsz;
+    out->kernel_variant = h->variant;
     return LBMP_OK;
 }
 

@@ -44,13 +44,15 @@ class Stats(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("min_p", ctypes.c_double),
                 ("max_cell_peclet", ctypes.c_double), ("min_stay", ctypes.c_double),
                 ("mean_velocity", ctypes.c_double * 3), ("tile_k", ctypes.c_int),
-                ("species_per_block", ctypes.c_int)]
+                ("species_per_block", ctypes.c_int), ("kernel_variant", ctypes.c_int)]
 
 
 EXPORTS = ["lbmp_last_error", "lbmp_version", "lb_flow_workspace_bytes", "lb_flow_solve",
            "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
            "mp_workspace_bytes", "mp_init", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
-           "mp_state", "mp_profile_steps", "mp_free"]
+           "mp_state", "mp_profile_steps", "mp_free", "sg_param_count", "sg_workspace_bytes",
+           "sg_create", "sg_set_params", "sg_get_params", "sg_set_normalization", "sg_train_step",
+           "sg_gradients", "sg_predict", "sg_sync", "sg_free"]
 
 _lib = None
 
@@ -84,6 +86,17 @@ def load_library(path: str = LIB_PATH):
         "mp_state": ([vp, i32, i32, vp, vp], i32),
         "mp_profile_steps": ([vp, i64, P(dbl), P(dbl)], i32),
         "mp_free": ([vp], None),
+        "sg_param_count": ([P(i64)], i32),
+        "sg_workspace_bytes": ([i32, P(sz)], i32),
+        "sg_create": ([i32, ctypes.c_uint64, vp, sz, vp, P(vp)], i32),
+        "sg_set_params": ([vp, vp], i32),
+        "sg_get_params": ([vp, vp], i32),
+        "sg_set_normalization": ([vp, vp, vp, ctypes.c_float, ctypes.c_float], i32),
+        "sg_train_step": ([vp, vp, vp, vp, i32, ctypes.c_float, vp], i32),
+        "sg_gradients": ([vp, vp, vp, i32, vp, vp], i32),
+        "sg_predict": ([vp, vp, i64, vp], i32),
+        "sg_sync": ([vp], i32),
+        "sg_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -294,7 +307,8 @@ def mp_stats(mp: MP, geom: int = 0) -> dict:
     return {"n_nodes": st.n_nodes, "n_fluid": st.n_fluid, "n_iface": st.n_iface,
             "lambda": st.lambda_, "min_p": st.min_p, "max_cell_peclet": st.max_cell_peclet,
             "min_stay": st.min_stay, "mean_velocity": list(st.mean_velocity),
-            "tile_k": st.tile_k, "species_per_block": st.species_per_block}
+            "tile_k": st.tile_k, "species_per_block": st.species_per_block,
+            "kernel_variant": st.kernel_variant}
 
 
 def mp_state(mp: MP, geom: int, species: int):
@@ -308,3 +322,78 @@ def mp_state(mp: MP, geom: int, species: int):
 
 def version() -> str:
     return load_library().lbmp_version().decode()
+
+
+# ---------------------------------------------------------------- surrogate
+class Surrogate:
+    """BF16-MFMA MLP (C-ABI sg_*): features (porosity, specific surface, Pe,
+    log10 k_a, log10 k_d, log10 t) -> log10(D_x(t)/D_b)."""
+
+    def __init__(self, batch_max: int = 1024, seed: int = 0, stream=None):
+        torch = _torch_cuda()
+        load_library()
+        nb = ctypes.c_size_t()
+        _check(_lib.sg_workspace_bytes(batch_max, ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream or torch.cuda.Stream()
+        self.batch_max = batch_max
+        h = ctypes.c_void_p()
+        _check(_lib.sg_create(batch_max, seed, ctypes.c_void_p(self.ws.data_ptr()), nb.value,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        _check(_lib.sg_param_count(ctypes.byref(n)))
+        self.n_params = n.value
+
+    def set_params(self, p: np.ndarray):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(_lib.sg_set_params(self.handle, _ptr(a)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.sg_get_params(self.handle, _ptr(a)))
+        return a
+
+    def set_normalization(self, x_mean, x_std, y_mean: float, y_std: float):
+        m = np.ascontiguousarray(x_mean, dtype=np.float32)
+        s = np.ascontiguousarray(x_std, dtype=np.float32)
+        _check(_lib.sg_set_normalization(self.handle, _ptr(m), _ptr(s), float(y_mean), float(y_std)))
+
+    def train_step(self, x, y, idx, B: int, lr: float, want_loss: bool = False):
+        """x, y: torch float32 CUDA tensors (n, 6), (n,); idx: int32 CUDA tensor (>= B) or None."""
+        loss = ctypes.c_float()
+        _check(_lib.sg_train_step(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                  ctypes.c_void_p(idx.data_ptr()) if idx is not None else None, int(B),
+                                  float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradients(self, x, y, B: int):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.sg_gradients(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 int(B), _ptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def predict(self, x, out=None):
+        """x: torch float32 CUDA tensor (n, 6) -> torch float32 CUDA tensor (n,)."""
+        torch = _torch_cuda()
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(_lib.sg_predict(self.handle, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sync(self):
+        _check(_lib.sg_sync(self.handle))
+
+    def free(self):
+        if self.handle:
+            _lib.sg_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

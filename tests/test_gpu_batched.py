@@ -19,8 +19,11 @@ def lb():
     return lbmp
 
 
-def d_err(D, Dref, db):
-    return float(np.max(np.abs(D - Dref) / np.maximum(np.abs(Dref), 1e-3 * db)))
+def d_err(D, Dref, db, prec=64):
+    """Largest |D - Dref| / max(|Dref|, floor): floor 1e-3 D_b for FP64 runs and
+    1e-2 D_b for FP32 storage, whose resolution of D is about 2^-24 Z(0)."""
+    floor = (1e-3 if prec == 64 else 1e-2) * db
+    return float(np.max(np.abs(D - Dref) / np.maximum(np.abs(Dref), floor)))
 
 
 def test_batched_slits_c3_full_length(lb):
@@ -49,7 +52,7 @@ def test_batched_slits_c3_full_length(lb):
                               qmask=2 | 8)
             Dref = oracle.d_of_t(ref["Z"], ref["V"])
             for gdir in (0, 2):
-                assert d_err(out["D"][s, gdir], Dref[gdir], db) < 1e-5, (W, s, gdir)
+                assert d_err(out["D"][s, gdir], Dref[gdir], db, 32) < 1e-5, (W, s, gdir)
     mp.free()
 
 
@@ -69,7 +72,7 @@ def test_batched_equals_separate_runs(lb):
         one = lb.mp_init(fl, {"D_b": 0.05, "k_a": ka[s:s + 1], "k_d": kd[s:s + 1]}, 32, T)
         lb.mp_step_n(one, T)
         o = lb.mp_vacf(one, 0)
-        assert d_err(both["D"][s], o["D"][0], 0.05) < 1e-6
+        assert d_err(both["D"][s], o["D"][0], 0.05, 32) < 1e-6
         one.free()
 
 
@@ -93,7 +96,7 @@ def test_porous_sphere_pack_with_bgk_flow(lb):
     for s in range(3):
         ref = oracle.vacf(m, rf["u"], 12 * db, ka[s], kd[s], T)
         Dref = oracle.d_of_t(ref["Z"], ref["V"])
-        assert d_err(out["D"][s], Dref, db) < 1e-5, s
+        assert d_err(out["D"][s], Dref, db, 32) < 1e-5, s
         assert np.allclose(out["mass"][s], ref["mass"][:, -1], rtol=1e-5, atol=1e-9)
     mp.free()
 
@@ -125,7 +128,7 @@ def test_degenerate_shapes(lb, shape):
         lb.mp_step_n(mp, T)
         out = lb.mp_vacf(mp, 0)
         ref = oracle.vacf(m, u, 0.48, 0.05, 0.1, T)
-        assert d_err(out["D"][0], oracle.d_of_t(ref["Z"], ref["V"]), 0.04) < tol
+        assert d_err(out["D"][0], oracle.d_of_t(ref["Z"], ref["V"]), 0.04, prec) < tol
         mp.free()
 
 

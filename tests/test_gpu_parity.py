@@ -1,10 +1,12 @@
 """GPU path vs the FP64 oracle, through the C-ABI (liblbmp.so).
 
 Tolerances: FP64 propagation must agree to rounding (1e-10 relative); FP32
-propagation with FP64 sums must satisfy
-|D_gpu - D_ref| <= 1e-5 * max(|D_ref|, 1e-3 D_b) at every recorded time
-(relative 1e-5, with a floor where D decays towards zero across a slit).
-Integer work (node classes, interface counts) must match exactly.
+storage (FP64 update, stochastic rounding) must satisfy
+|D_gpu - D_ref| <= 1e-5 * max(|D_ref|, 1e-2 D_b) at every recorded time:
+1e-5 relative wherever D >= D_b/100, and 1e-7 D_b absolute where D decays
+towards zero across a slit (FP32 holds the velocity-weighted start only to
+2^-24 of Z(0), about 6e-8 D_b). Integer work (node classes, interface
+counts) must match exactly.
 """
 import numpy as np
 import pytest
@@ -25,8 +27,11 @@ def lb():
     return lbmp
 
 
-def d_err(D, Dref, db):
-    return float(np.max(np.abs(D - Dref) / np.maximum(np.abs(Dref), 1e-3 * db)))
+def d_err(D, Dref, db, prec=64):
+    """Largest |D - Dref| / max(|Dref|, floor): floor 1e-3 D_b for FP64 runs and
+    1e-2 D_b for FP32 storage, whose resolution of D is about 2^-24 Z(0)."""
+    floor = (1e-3 if prec == 64 else 1e-2) * db
+    return float(np.max(np.abs(D - Dref) / np.maximum(np.abs(Dref), floor)))
 
 
 # ---------------------------------------------------------------- geometry
@@ -98,7 +103,7 @@ def test_slit_c1_full_length(lb, prec):
     out = run_gpu(lb, flow, {"Delta": 0.5, "k_a": [0.01], "k_d": [0.01]}, prec, T)
     D = out["D"][0]
     tol = 1e-10 if prec == 64 else 1e-5
-    assert d_err(D, Dref, db) < tol
+    assert d_err(D, Dref, db, prec) < tol
     # lattice closed form for the direction along the walls
     assert np.abs(D[0] / db - (20 + 2 * 5 / 6) / 24).max() < (1e-12 if prec == 64 else 1e-6)
     assert abs(out["mass"].sum() - 1) < (1e-13 if prec == 64 else 1e-6)
@@ -120,7 +125,7 @@ def test_random_porous_random_flow(lb, prec):
     for s in range(3):
         ref = oracle.vacf(m, u, lam, ka[s], kd[s], T)
         Dref = oracle.d_of_t(ref["Z"], ref["V"])
-        assert d_err(out["D"][s], Dref, lam / 12) < (1e-10 if prec == 64 else 1e-5)
+        assert d_err(out["D"][s], Dref, lam / 12, prec) < (1e-10 if prec == 64 else 1e-5)
         zs = np.abs(ref["Z"]).max()
         assert np.abs(out["Z"][s] - ref["Z"]).max() < (1e-12 if prec == 64 else 1e-6) * zs
         assert np.allclose(out["vbar"][s], ref["V"], rtol=1e-6 if prec == 32 else 1e-12, atol=1e-15)
@@ -162,4 +167,31 @@ def test_poiseuille_c2_full_length_fp32(lb, pe):
     Dref = oracle.d_of_t(ref["Z"], ref["V"])
     D = out["D"][0]
     for gdir in (0, 2):
-        assert d_err(D[gdir], Dref[gdir], db) < 1e-5, gdir
+        assert d_err(D[gdir], Dref[gdir], db, 32) < 1e-5, gdir
+
+
+@pytest.mark.parametrize("tile", ["0,1,1", "0,2,3", "1,1,2", "1,2,5", "1,2,8", "2,8,1", "2,3,2", "2,16,4", "2,2,4"])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_kernel_variants(lb, monkeypatch, tile, prec):
+    """Every step-kernel variant (direct / LDS-staged, K z-planes per thread,
+    species per block) on a ragged porous lattice (nx not a multiple of 64,
+    ny not of 4, nz not of K, species not of the group size) vs the oracle."""
+    monkeypatch.setenv("LBMP_TILE", tile)
+    m = inputs.random_mask(70, 9, 7, 0.3, seed=21)
+    u = inputs.random_velocity(m, 0.02, seed=22)
+    ka = np.array([0.0, 0.02, 0.1, 0.005, 0.3])
+    kd = np.array([0.1, 0.01, 0.2, 0.5, 0.9])
+    T = 150
+    flow = lb.lb_flow_from_velocity(m, u)
+    mp = lb.mp_init(flow, {"D_b": 0.06, "k_a": ka, "k_d": kd}, prec, T)
+    st = lb.mp_stats(mp, 0)
+    v, K, gs = (int(c) for c in tile.split(","))
+    assert (st["kernel_variant"], st["tile_k"], st["species_per_block"]) == (v, K, gs)
+    lb.mp_step_n(mp, T)
+    out = lb.mp_vacf(mp, 0)
+    for s in range(5):
+        ref = oracle.vacf(m, u, 0.72, ka[s], kd[s], T)
+        Dref = oracle.d_of_t(ref["Z"], ref["V"])
+        assert d_err(out["D"][s], Dref, 0.06, prec) < (1e-10 if prec == 64 else 1e-5), s
+        assert np.allclose(out["mass"][s], ref["mass"][:, -1], rtol=1e-12 if prec == 64 else 1e-5)
+    mp.free()

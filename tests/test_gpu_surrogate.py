@@ -1,0 +1,133 @@
+"""Surrogate network kernels (BF16 MFMA, FP32 accumulation) vs the FP64 reference.
+
+BF16 operands carry 8 significant bits, so outputs and gradients are compared
+norm-wise: ||gpu - ref|| <= 2e-2 ||ref|| per tensor.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1303_2470_amd import lbmp
+    lbmp.load_library()
+    return lbmp
+
+
+def flat(params):
+    return np.concatenate([p.reshape(-1) for p in params]).astype(np.float32)
+
+
+def unflat(v, like):
+    out, k = [], 0
+    for p in like:
+        out.append(v[k:k + p.size].reshape(p.shape))
+        k += p.size
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_param_count(lb):
+    sg = lb.Surrogate(64, seed=1)
+    assert sg.n_params == 133633 == sum(p.size for p in mlp.init_params(0))
+    p = sg.get_params()
+    assert np.abs(p[: 256 * 6]).max() <= 1 / np.sqrt(6) + 1e-7
+    sg.free()
+
+
+@pytest.mark.parametrize("B", [32, 256, 1024])
+def test_forward_matches_reference(lb, B):
+    import torch
+    params = mlp.init_params(5)
+    rng = np.random.default_rng(B)
+    x = rng.normal(size=(B, 6))
+    sg = lb.Surrogate(1024, seed=0)
+    sg.set_params(flat(params))
+    assert np.array_equal(sg.get_params(), flat(params))
+    y = sg.predict(torch.tensor(x, dtype=torch.float32, device="cuda"))
+    sg.sync()
+    yref, _ = mlp.forward(params, x)
+    assert rel(y.cpu().numpy().astype(np.float64), yref) < 2e-2
+    sg.free()
+
+
+def test_predict_ragged_and_normalisation(lb):
+    """n not a multiple of 32 nor of the batch size; z-scoring applied on the device."""
+    import torch
+    params = mlp.init_params(6)
+    rng = np.random.default_rng(1)
+    n = 1000
+    x = rng.normal(size=(n, 6)) * 3 + 1
+    mu, sd = x.mean(axis=0), x.std(axis=0)
+    sg = lb.Surrogate(256, seed=0)
+    sg.set_params(flat(params))
+    sg.set_normalization(mu, sd, 0.5, 2.0)
+    y = sg.predict(torch.tensor(x, dtype=torch.float32, device="cuda"))
+    sg.sync()
+    yref, _ = mlp.forward(params, (x - mu) / sd)
+    assert rel(y.cpu().numpy(), 0.5 + 2.0 * yref) < 2e-2
+    sg.free()
+
+
+def test_gradients_match_reference(lb):
+    import torch
+    params = mlp.init_params(7)
+    rng = np.random.default_rng(3)
+    B = 512
+    x = rng.normal(size=(B, 6))
+    t = np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2]
+    sg = lb.Surrogate(B, seed=0)
+    sg.set_params(flat(params))
+    g, loss = sg.gradients(torch.tensor(x, dtype=torch.float32, device="cuda"),
+                           torch.tensor(t, dtype=torch.float32, device="cuda"), B)
+    lref, gref = mlp.loss_and_grads(params, x, t)
+    assert abs(loss / lref - 1) < 2e-2
+    for a, b in zip(unflat(g, params), gref):
+        assert rel(a, b) < 2e-2
+
+
+def test_training_fits_smooth_function(lb):
+    """Adam on the GPU drives the loss of a smooth 6-feature target down and
+    tracks the FP64 reference trajectory for the first steps."""
+    import torch
+    rng = np.random.default_rng(11)
+    n, B = 8192, 512
+    x = rng.uniform(-1, 1, size=(n, 6))
+    t = np.tanh(x[:, 0] + 0.5 * x[:, 1]) + 0.2 * x[:, 2] * x[:, 3] - 0.1 * x[:, 4] + 0.05 * x[:, 5]
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    params = mlp.init_params(2)
+    sg = lb.Surrogate(B, seed=0)
+    sg.set_params(flat(params))
+    # first 5 steps on the first B rows vs the FP64 reference
+    m = [np.zeros_like(p) for p in params]
+    v = [np.zeros_like(p) for p in params]
+    ref = [p.copy() for p in params]
+    for k in range(1, 6):
+        sg.train_step(xt, tt, None, B, 1e-3)
+        _, gr = mlp.loss_and_grads(ref, x[:B], t[:B])
+        mlp.adam_step(ref, gr, m, v, k, 1e-3)
+    got = unflat(sg.get_params(), params)
+    for a, b, p0 in zip(got, ref, params):
+        assert rel(a - p0, b - p0) < 5e-2       # the update itself, BF16 gradients
+    losses = []
+    for ep in range(30):
+        perm = torch.tensor(rng.permutation(n).astype(np.int32), device="cuda")
+        for i in range(n // B):
+            l = sg.train_step(xt, tt, perm[i * B:], B, 1e-3, want_loss=(i == n // B - 1))
+        losses.append(l)
+    assert losses[-1] < 0.05 * float(np.var(t))
+    y = sg.predict(xt)
+    sg.sync()
+    assert float(np.mean((y.cpu().numpy() - t) ** 2)) < 0.05 * float(np.var(t))
+    sg.free()
