@@ -497,10 +497,9 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
                                                   int64_t nblocks, int zseg, const Ctl* __restrict__ ctl) {
     constexpr int F = 4 * G;
     using R = Ring<F>;
-    static_assert(NRED * BLK * sizeof(double) <= 3 * F * R::PL * sizeof(T) + 4096,
-                  "reduction scratch must fit in the plane ring");
-    __shared__ __align__(16) char smem[3 * F * R::PL * sizeof(T) > NRED * BLK * sizeof(double)
-                                           ? 3 * F * R::PL * sizeof(T) : NRED * BLK * sizeof(double)];
+    constexpr size_t RING_BYTES = 3 * F * R::PL * sizeof(T);
+    constexpr size_t RED_BYTES = NRED * BLK * sizeof(double);
+    __shared__ __align__(16) char smem[RING_BYTES > RED_BYTES ? RING_BYTES : RED_BYTES];
     T* ring = reinterpret_cast<T*>(smem);  // [3][F][PL]
     constexpr int E = (int)sizeof(T);
     T* const tag = nullptr;
@@ -523,43 +522,44 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
     const bool inplane = x < nx && y < ny;
     const int c0 = (ly + 1) * R::PX + (lx + 1);  // this thread's column in a haloed plane
     const int own = inplane ? y * nx + x : 0;
-    // this thread's share of a haloed plane: in-plane offsets (wrapped)
     int poff[R::LOADS];
 #pragma unroll
     for (int i = 0; i < R::LOADS; ++i) {
         const int e = tid + i * BLK;
-        if (e < R::PL) {
-            const int yy = e / R::PX, xx = e % R::PX;
-            poff[i] = modp(y0 - 1 + yy, ny) * nx + modp(x0 - 1 + xx, nx);
-        } else {
-            poff[i] = -1;
-        }
+        poff[i] = e < R::PL ? modp(y0 - 1 + e / R::PX, ny) * nx + modp(x0 - 1 + e % R::PX, nx) : -1;
     }
     const int64_t t = ctl->t;
     const T* Xin = (t & 1) ? Gm.X1 : Gm.X0;
     T* Xout = (t & 1) ? Gm.X0 : Gm.X1;
     const int s0 = grp * G, ns = min(G, Gm.S - s0);
-    const int64_t NI = Gm.NI;
+    const int NI = (int)Gm.NI;
     const uint32_t tseed = hash32((uint32_t)t ^ ((uint32_t)gi << 24));
-
-    // plane pz of every field of the group -> registers
-    // one resource per array: the group's fields of X, the group's adsorbed
-    // fields, the link table; the field (or link) index goes to the scalar offset
+    // one resource per array; field / link index in the scalar offset. Fields
+    // beyond the group's species count read 0 and are never stored.
     const auto rin = mkrsrc(Xin + (int64_t)(4 * s0) * N, (int64_t)(4 * ns) * N * E);
     const auto rout = mkrsrc(Xout + (int64_t)(4 * s0) * N, (int64_t)(4 * ns) * N * E);
     const auto rads = mkrsrc(Gm.Xa + (int64_t)(4 * s0) * NI, (int64_t)(4 * ns) * NI * E);
     const auto rpin = mkrsrc(Gm.pin, (int64_t)NL * N * E);
     const auto ra = mkrsrc(Gm.a, (int64_t)3 * N * E);
+    const auto rsig = mkrsrc(Gm.sig, (int64_t)N * 8);
+    const auto rsrc = mkrsrc(Gm.src, (int64_t)N * E);
+    const auto rcls = mkrsrc(Gm.cls, (int64_t)N);
+    const auto rslot = mkrsrc(Gm.slot, (int64_t)N * 4);
+    double pa[G], pd[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int s = min(s0 + g, Gm.S - 1);
+        pa[g] = (double)Gm.prob[2 * s];
+        pd[g] = (double)Gm.prob[2 * s + 1];
+    }
+
     auto fetch = [&](int pz, T (&reg)[F][R::LOADS]) {
         const int zo = modp(pz, nz) * plane;
-        int vo[R::LOADS];
-#pragma unroll
-        for (int i = 0; i < R::LOADS; ++i) vo[i] = poff[i] >= 0 ? (zo + poff[i]) * E : OOB;
 #pragma unroll
         for (int f = 0; f < F; ++f)
 #pragma unroll
             for (int i = 0; i < R::LOADS; ++i)
-                reg[f][i] = f < 4 * ns ? bload(tag, rin, vo[i], f * N * E) : T(0);
+                reg[f][i] = bload(tag, rin, (f < 4 * ns && poff[i] >= 0) ? (zo + poff[i]) * E : OOB, f * N * E);
     };
     auto stash = [&](int slot, const T (&reg)[F][R::LOADS]) {
 #pragma unroll
@@ -570,6 +570,36 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
                 if (e < R::PL) ring[(slot * F + f) * R::PL + e] = reg[f][i];
             }
     };
+    // node classes two planes ahead, link data and adsorbed values one plane ahead
+    auto cls_of = [&](int z) -> int {  // -1: no active node
+        if (!inplane || z >= ze) return -1;
+        const int n = z * plane + own;
+        const int c = (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(rcls, n, 0, 0);
+        return c != 0 ? n : -1;
+    };
+    struct Link {
+        T pin[NL], src, a[3];
+        double sig;
+        T xa[F];
+        int n, sl;
+    };
+    auto load_link = [&](int n, int sl, Link& L) {
+        const int on = n >= 0 ? n * E : OOB, oa = sl >= 0 ? sl * E : OOB;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) L.pin[k] = bload(tag, rpin, on, k * N * E);
+        L.sig = bload(dtag, rsig, n >= 0 ? n * 8 : OOB);
+        L.src = bload(tag, rsrc, on);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) L.a[g] = bload(tag, ra, on, g * N * E);
+#pragma unroll
+        for (int f = 0; f < F; ++f) L.xa[f] = bload(tag, rads, f < 4 * ns ? oa : OOB, f * NI * E);
+        L.n = n;
+        L.sl = sl;
+    };
+    auto slot_of = [&](int n) -> int {
+        return n >= 0 ? (int)__builtin_amdgcn_raw_buffer_load_b32(rslot, n * 4, 0, 0) : -1;
+    };
+
     T pre[F][R::LOADS];
     fetch(zs - 1, pre);
     stash(0, pre);
@@ -577,6 +607,13 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
     stash(1, pre);
     fetch(zs + 1, pre);
     stash(2, pre);
+    Link cur, nxt;
+    int n1 = cls_of(zs + 1);         // node of plane zs+1
+    {
+        const int n0 = cls_of(zs);
+        load_link(n0, slot_of(n0), cur);
+    }
+    int sl1 = slot_of(n1);
     __syncthreads();
 
     double red[G][NRED];
@@ -587,59 +624,56 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 
     for (int z = zs; z < ze; ++z) {
         const int sm = (z - zs) % 3, sc = (z - zs + 1) % 3, sp = (z - zs + 2) % 3;
-        // link data of this thread's node (x, y, z)
-        const int n = z * plane + own;
-        const bool act = inplane && Gm.cls[n] != 0;
-        const int sl = act ? Gm.slot[n] : -1;
-        const bool isI = sl >= 0;
-        const int offn = act ? n * E : OOB, offa = isI ? sl * E : OOB;
+        const bool more = z + 1 < ze;
+        // in flight while plane z is updated: plane z+2 of every field, the
+        // link data and adsorbed values of node z+1, the class of node z+2
+        if (more) fetch(z + 2, pre);
+        load_link(n1, sl1, nxt);
+        const int n2 = cls_of(z + 2);
+        const int sl2 = slot_of(n2);
+
+        const bool act = cur.n >= 0, isI = cur.sl >= 0;
+        const int offn = act ? cur.n * E : OOB, offa = isI ? cur.sl * E : OOB;
         double pin[NL];
 #pragma unroll
-        for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, rpin, offn, k * N * E);
-        const double sig = bload(dtag, mkrsrc(Gm.sig, (int64_t)N * 8), act ? n * 8 : OOB);
-        const double src = (double)bload(tag, mkrsrc(Gm.src, (int64_t)N * E), offn);
-        double av[3];
-#pragma unroll
-        for (int g = 0; g < 3; ++g) av[g] = (double)bload(tag, ra, offn, g * N * E);
-        // plane z+2 in flight while plane z is updated
-        const bool more = z + 1 < ze;
-        if (more) fetch(z + 2, pre);
-        const uint32_t rnode = hash32((uint32_t)n * 0x9e3779b9u ^ tseed);
+        for (int k = 0; k < NL; ++k) pin[k] = (double)cur.pin[k];
+        const double sig = cur.sig, src = (double)cur.src;
+        const uint32_t rnode = hash32((uint32_t)(z * plane + own) * 0x9e3779b9u ^ tseed);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (g >= ns) break;
             const int s = s0 + g;
-            const double pa = (double)Gm.prob[2 * s], pd = (double)Gm.prob[2 * s + 1];
+            const double pag = isI ? pa[g] : 0.0;
             uint32_t rs = hash32(rnode ^ ((uint32_t)s * 0x632be5abu)) | 1u;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int f = 4 * g + q;
-                const int64_t fg = 4 * s + q;
-                const double xa = (double)bload(tag, rads, offa, f * (int)NI * E);
                 const T* pm = ring + (sm * F + f) * R::PL;
                 const T* pc = ring + (sc * F + f) * R::PL;
                 const T* pp = ring + (sp * F + f) * R::PL;
-                double acc = 0.0;
+                double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
                 for (int k = 0; k < NL; ++k) {
                     const int o = c0 - lcy(k) * R::PX - lcx(k);
                     const T v = lcz(k) > 0 ? pm[o] : (lcz(k) < 0 ? pp[o] : pc[o]);
-                    acc = __builtin_fma((double)v, pin[k], acc);
+                    if (k & 1) acc1 = __builtin_fma((double)v, pin[k], acc1);
+                    else acc0 = __builtin_fma((double)v, pin[k], acc0);
                 }
                 const double xc = (double)pc[c0];
-                const double fa = isI ? pa * xc : 0.0;
-                const double fd = pd * xa;
+                const double xa = (double)cur.xa[f];
+                const double fa = pag * xc;
+                const double fd = pd[g] * xa;
                 double nv = __builtin_fma(-xc, sig, xc);
-                nv = __builtin_fma((double)Gm.coef[fg], src, (nv - fa) + fd) + acc;
+                nv = __builtin_fma((double)Gm.coef[4 * min(s, Gm.S - 1) + q], src, (nv - fa) + fd) + (acc0 + acc1);
                 const uint32_t r1 = xorshift32(rs);
-                bstore(store_round<T>(nv, r1), rout, offn, f * N * E);
-                bstore(store_round<T>((xa + fa) - fd, (r1 >> 3) | (r1 << 29)), rads, offa, f * (int)NI * E);
+                const int so = f < 4 * ns ? 0 : OOB;  // partial group: no store
+                bstore(store_round<T>(nv, r1), rout, offn | so, f * N * E);
+                bstore(store_round<T>((xa + fa) - fd, (r1 >> 3) | (r1 << 29)), rads, offa | so, f * NI * E);
                 const double xd = act ? xc : 0.0;
                 if (q == 0) {
                     red[g][3] += xd;
                     red[g][7] += xa;
                 } else {
-                    red[g][q - 1] = __builtin_fma(xd, av[q - 1], red[g][q - 1]);
+                    red[g][q - 1] = __builtin_fma(xd, (double)cur.a[q - 1], red[g][q - 1]);
                     red[g][3 + q] += xd + xa;
                 }
             }
@@ -647,16 +681,18 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
         __syncthreads();          // every read of plane z-1 is done
         if (more) stash(sm, pre); // plane z+2 takes its slot
         __syncthreads();
+        cur = nxt;
+        n1 = n2;
+        sl1 = sl2;
     }
     // the ring is free: reuse it for the block sums
     double* lds = reinterpret_cast<double*>(smem);
     const int64_t ntile = Gm.ntile;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (g >= ns) break;
         double r;
         block_sum8(red[g], lds, r);
-        if (tid < NRED) Gm.part[((int64_t)(s0 + g) * ntile + tile) * NRED + tid] = r;
+        if (tid < NRED && g < ns) Gm.part[((int64_t)(s0 + g) * ntile + tile) * NRED + tid] = r;
     }
 }
 

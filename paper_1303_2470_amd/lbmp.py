@@ -64,6 +64,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    # PyTorch-ROCm ships its own HIP runtime; load it first so that liblbmp
+    # binds to the same runtime that owns the workspaces and streams
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     P = ctypes.POINTER

@@ -161,6 +161,45 @@ def evaluate(sg, X: np.ndarray, Y: np.ndarray) -> dict:
             "max": float(rel.max()), "frac_within_2pct": float(np.mean(rel < 0.02)), "rows": int(len(Y))}
 
 
+def query(lb, sg, mask: np.ndarray, peclet: float, k_a, k_d, times, velocity: np.ndarray | None = None):
+    """D_x(t)/D_b for species (k_a[i], k_d[i]) in a medium at Peclet `peclet`.
+
+    In-domain queries are answered by the network; if any feature lies outside
+    the training domain the plain method runs instead (flow from `velocity` if
+    given, otherwise the BGK solution rescaled to the Peclet number).
+    Returns (D/D_b array (n_species, n_times), "surrogate" | "method")."""
+    import torch
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    k_a = np.atleast_1d(np.asarray(k_a, dtype=np.float64))
+    k_d = np.atleast_1d(np.asarray(k_d, dtype=np.float64))
+    times = np.atleast_1d(np.asarray(times, dtype=np.int64))
+    fluid = mask == 0
+    # interface share from the library's own classification
+    fl = lb.lb_flow_from_velocity(mask, np.zeros((3,) + mask.shape))
+    _, nf, ni = fl.classes()
+    fl.free()
+    feats = np.array([[nf / mask.size, ni / mask.size, peclet, math.log10(a), math.log10(d), math.log10(t)]
+                      for a, d in zip(k_a, k_d) for t in times])
+    if in_domain(feats).all() and (k_a > 0).all() and (times >= 1).all():
+        y = sg.predict(torch.tensor(feats, dtype=torch.float32, device="cuda"))
+        sg.sync()
+        return 10.0 ** y.cpu().numpy().reshape(len(k_a), len(times)), "surrogate"
+    if velocity is None:
+        ref = lb.lb_flow_solve(mask, 1.0, [G_REF, 0.0, 0.0], 1e-8, 200000)
+        u = ref.velocity()
+        ref.free()
+        vbar = float(u[0][fluid].mean())
+        velocity = u * ((peclet * D_B / mask.shape[2]) / vbar if vbar > 0 else 0.0)
+    flow = lb.lb_flow_from_velocity(mask, velocity)
+    tmax = int(times.max())
+    mp = lb.mp_init(flow, {"D_b": D_B, "k_a": k_a, "k_d": k_d}, lb.LBMP_FP32, tmax)
+    lb.mp_step_n(mp, tmax)
+    out = lb.mp_vacf(mp, 0, 0, tmax + 1)
+    mp.free()
+    flow.free()
+    return out["D"][:, 0, times] / D_B, "method"
+
+
 def _batches_by_radius(seeds, batch):
     """Groups with the same sphere radius share a time horizon; batch them together."""
     by_r = {}

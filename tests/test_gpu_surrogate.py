@@ -131,3 +131,31 @@ def test_training_fits_smooth_function(lb):
     sg.sync()
     assert float(np.mean((y.cpu().numpy() - t) ** 2)) < 0.05 * float(np.var(t))
     sg.free()
+
+
+def test_dataset_rows_and_fallback(lb):
+    """One group of the surrogate workload (64^3 sphere pack): feature rows are
+    finite and inside the training domain; a query outside the domain falls
+    back to the method and equals a direct run."""
+    from paper_1303_2470_amd import inputs, surrogate
+    g = surrogate.group_params(5)
+    g["R"] = 4                                     # short horizon for the test
+    X, Y, info = surrogate.run_groups(lb, [g])
+    assert X.shape[1] == 6 and len(X) == len(Y) > 8 * 20
+    assert np.isfinite(X).all() and np.isfinite(Y).all()
+    assert surrogate.in_domain(X).all()
+    assert info["steps"] == surrogate.sample_times(4)[-1]
+    sg = lb.Surrogate(256, seed=1)
+    mask = inputs.sphere_pack(32, 4, 0.5, seed=3)
+    u = inputs.random_velocity(mask, 0.005, seed=4)
+    D, how = surrogate.query(lb, sg, mask, 10.0, [0.5], [0.01], [1, 10, 100], velocity=u)  # k_a out of domain
+    assert how == "method"
+    fl = lb.lb_flow_from_velocity(mask, u)
+    mp = lb.mp_init(fl, {"D_b": surrogate.D_B, "k_a": [0.5], "k_d": [0.01]}, 32, 100)
+    lb.mp_step_n(mp, 100)
+    ref = lb.mp_vacf(mp, 0)["D"][0, 0, [1, 10, 100]] / surrogate.D_B
+    assert np.allclose(D[0], ref, rtol=1e-6)
+    D2, how2 = surrogate.query(lb, sg, mask, 10.0, [0.01, 0.001], [0.01, 0.05], [1, 10, 100])
+    assert how2 == "surrogate" and D2.shape == (2, 3) and np.isfinite(D2).all()
+    mp.free()
+    sg.free()
