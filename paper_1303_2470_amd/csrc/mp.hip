@@ -29,6 +29,7 @@
 #include <cmath>
 #include <map>
 #include <tuple>
+#include <type_traits>
 
 #include "lbmp_internal.hpp"
 
@@ -696,6 +697,236 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
     }
 }
 
+// ------------------------------------------------------------------ variant 3
+// FP32 storage. For every field (species, quantity) of the block, the stencil
+// region — planes z-1, z and z+1 of a TX x TY tile with a one-node periodic
+// halo — and the tile's adsorbed values are copied by the buffer unit straight
+// into LDS (buffer_load ... lds: lane i of a wave fills dword i of the wave's
+// destination; a lane out of range writes 0), three fields ahead of the field
+// being updated, through four LDS stages (stage = quantity q). Nothing passes
+// through registers on its way in, so the tile's link data stay in registers
+// for all the fields of the block. Tiles run z-fastest and the species groups
+// of a tile are adjacent, so the blocks that read a plane as centre and as
+// z-neighbour, and the blocks that share a tile's link data, are resident
+// together. Waves without an interface node skip the sorption arithmetic.
+constexpr int RX = TX + 2, RPL = RX * (TY + 2);  // one haloed plane
+constexpr int RREG = 3 * RPL;                    // planes z-1, z, z+1
+constexpr int RLD = (RREG + BLK - 1) / BLK;      // region loads per thread and field
+constexpr int STAGE = (RLD + 1) * BLK;           // dwords: region, then adsorbed values
+constexpr int DMA_GMAX = 64;                     // species per block
+
+#define LBMP_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+// s_waitcnt immediate: vmcnt(c), no expcnt wait, lgkmcnt(0)
+#define LBMP_WAIT_VM_LGKM0(c) __builtin_amdgcn_s_waitcnt(((c) & 15) | ((((c) >> 4) & 3) << 14) | 0x0070)
+
+// Block-wide barrier after this wave's LDS traffic has completed and at most
+// n of its vector-memory operations (which complete in issue order) are
+// outstanding. The empty asm statements keep the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void barrier_vm(int n) {
+    asm volatile("" ::: "memory");
+    if (n >= 16) LBMP_WAIT_VM_LGKM0(16);
+    else if (n >= 14) LBMP_WAIT_VM_LGKM0(14);
+    else if (n >= 12) LBMP_WAIT_VM_LGKM0(12);
+    else if (n >= 10) LBMP_WAIT_VM_LGKM0(10);
+    else if (n >= 5) LBMP_WAIT_VM_LGKM0(5);
+    else LBMP_WAIT_VM_LGKM0(0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Four LDS stages as separate objects, so that the compiler's own tracking of
+// LDS DMA can tell a stage being read from the stages still being filled.
+struct Stages {
+    float* p[4];
+    template <int Q>
+    __device__ __forceinline__ float* at() const { return p[Q]; }
+};
+
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
+                                               int64_t nblocks, const Ctl* __restrict__ ctl) {
+    __shared__ __align__(16) float st0[STAGE];
+    __shared__ __align__(16) float st1[STAGE];
+    __shared__ __align__(16) float st2[STAGE];
+    __shared__ __align__(16) float st3[STAGE];
+    __shared__ __align__(16) double rl[4 * BLK];  // block sums, half of them at a time
+    __shared__ float spt[6 * DMA_GMAX];  // per species of the group: p_a, p_d, c_0..c_3
+    float* const tag = nullptr;
+    const int64_t lb = xcd_remap(blockIdx.x, nblocks);
+    const int gi = find_geom(geoms, ngeom, lb);
+    const GeomDev<float>& G = geoms[gi];
+    const int64_t local = lb - G.blk0;
+    const int grp = (int)(local % G.ngrp);
+    const int64_t tile = local / G.ngrp;
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int ntx = (nx + TX - 1) / TX;
+    const int z = (int)(tile % nz);
+    const int64_t cxy = tile / nz;
+    const int x0 = (int)(cxy % ntx) * TX, y0 = (int)(cxy / ntx) * TY;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inplane = x < nx && y < ny;
+    const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
+    const int n = z * plane + (inplane ? y * nx + x : 0);
+    const bool act = inplane && G.cls[n] != 0;
+    const int sl = act ? G.slot[n] : -1;
+    const bool isI = sl >= 0;
+    const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
+    const int offn = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
+    // this thread's share of the stencil region, element e = j * BLK + tid
+    int voff[RLD];
+#pragma unroll
+    for (int j = 0; j < RLD; ++j) {
+        const int e = j * BLK + tid;
+        const int pz = e / RPL, r = e % RPL, hy = r / RX, hx = r % RX;
+        voff[j] = e < RREG ? (modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx)) * 4
+                           : OOB;
+    }
+    double pin[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offn);
+    const double sig = __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, (int64_t)N * 8), act ? n * 8 : OOB, 0, 0));
+    const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offn);
+    float av[3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offn);
+    const int64_t t = ctl->t;
+    const uint32_t rbase = hash32((uint32_t)n * 0x9e3779b9u ^ hash32((uint32_t)t ^ ((uint32_t)gi << 24)));
+    const float* const Xin = (t & 1) ? G.X1 : G.X0;
+    float* const Xout = (t & 1) ? G.X0 : G.X1;
+    float* const Xa = G.Xa;
+    const float* const coef = G.coef;
+    const float* const prob = G.prob;
+    double* const part = G.part;
+    const int64_t ntile = G.ntile;
+    const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
+    const int fb = 4 * s0, fe = 4 * s1;
+    const int nL = anyI ? RLD + 1 : RLD, nS = anyI ? 2 : 1;  // per field: DMA loads, stores
+    const Stages stg{{st0, st1, st2, st3}};
+    // species constants through LDS: read in the loop as vector loads they
+    // would queue behind the DMA in flight
+    for (int i = tid; i < 6 * (s1 - s0); i += BLK) {
+        const int sp = s0 + i / 6, c = i % 6;
+        spt[i] = c < 2 ? prob[2 * sp + c] : coef[4 * sp + c - 2];
+    }
+
+    auto issue = [&](int f, float* stq) {
+        const auto rin = mkrsrc(Xin + (int64_t)f * N, (int64_t)N * 4);
+        float* dst = stq + wv * 64;
+#pragma unroll
+        for (int j = 0; j < RLD; ++j)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * BLK), 4, voff[j], 0, 0, 0);
+        if (anyI)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
+                                                     LBMP_LDS(dst + RLD * BLK), 4, offa, 0, 0, 0);
+    };
+    // Fixed-order block sums k0..k0+3 of species s from rl: wave w forms sum
+    // k0 + w. The eight sums of a species go through rl in two halves (sums
+    // 0-3 at the species' end, read after the next barrier; sums 4-7 written
+    // after the following barrier and read after the one after that).
+    auto reduce4 = [&](int s, int k0) {
+        const int l = tid & 63;
+        const double* p = rl + wv * BLK + l * 4;
+        double v = ((p[0] + p[1]) + p[2]) + p[3];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        // a buffer store: a flat store would also count as LDS traffic and
+        // make the next LDS read wait for every DMA in flight
+        bstore(v, mkrsrc(part + (int64_t)s * ntile * NRED, ntile * NRED * 8),
+               l == 0 ? (int)(tile * NRED + k0 + wv) * 8 : OOB);
+    };
+    double hold[4];  // sums 4-7 of species pendH until they enter rl
+
+    issue(fb, st0);
+    if (fb + 1 < fe) issue(fb + 1, st1);
+    if (fb + 2 < fe) issue(fb + 2, st2);
+    const int cb = ly * RX + lx;  // region index of (x-1, y-1) in plane z-1
+    int pendA = -1, pendH = -1, pendB = -1;  // species with sums 0-3 in rl, 4-7 held, 4-7 in rl
+    for (int s = s0; s < s1; ++s) {
+        double red[NRED];
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) red[k] = 0.0;
+        auto field = [&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int f = 4 * s + q;
+            // field f has landed for the whole block once this wave has at most
+            // the operations issued after it outstanding: the loads of f+1, f+2
+            // and the stores of f-2, f-1
+            barrier_vm(nL * (min(f + 2, fe - 1) - f) + nS * (f - max(fb, f - 2)));
+            if constexpr (q == 0) if (pendA >= 0) {
+                reduce4(pendA, 0);
+                pendA = -1;
+            }
+            if constexpr (q == 1) if (pendH >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) rl[k * BLK + tid] = hold[k];
+                pendB = pendH;
+                pendH = -1;
+            }
+            if constexpr (q == 2) if (pendB >= 0) {
+                reduce4(pendB, 4);
+                pendB = -1;
+            }
+            // one live base index: addresses derived from it are not hoisted
+            // out of the loop (each would hold a register for the whole loop)
+            int c = cb;
+            asm volatile("" : "+v"(c));
+            const float* sb = stg.at<q>() + c;
+            const float* sp = spt + 6 * (s - s0);
+            const double pa = (double)sp[0], pd = (double)sp[1];
+            const double xc = (double)sb[RPL + RX + 1];
+            double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
+            double xa = 0.0, fa = 0.0, fd = 0.0;
+            if (anyI) {
+                xa = (double)stg.at<q>()[RLD * BLK + tid];
+                fa = isI ? pa * xc : 0.0;  // adsorption (Eq. 9)
+                fd = pd * xa;              // desorption (Eq. 10)
+                acc0 = (acc0 - fa) + fd;
+            }
+            acc0 = __builtin_fma((double)sp[2 + q], src, acc0);
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
+                const int o = (1 - lcz(k)) * RPL + (1 - lcy(k)) * RX + (1 - lcx(k));
+                if (k & 1) acc1 = __builtin_fma((double)sb[o], pin[k], acc1);
+                else acc0 = __builtin_fma((double)sb[o], pin[k], acc0);
+            }
+            const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
+            bstore(sround(acc0 + acc1, r), mkrsrc(Xout + (int64_t)f * N, (int64_t)N * 4), offn);
+            if (anyI)
+                bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
+                       offa);
+            const double xd = act ? xc : 0.0;
+            if constexpr (q == 0) {
+                red[3] += xd;
+                red[7] += xa;
+            } else {
+                red[q - 1] = __builtin_fma(xd, (double)av[q - 1], red[q - 1]);
+                red[3 + q] += xd + xa;
+            }
+            if (f + 3 < fe) issue(f + 3, stg.at<(q + 3) & 3>());
+        };
+        field(std::integral_constant<int, 0>());
+        field(std::integral_constant<int, 1>());
+        field(std::integral_constant<int, 2>());
+        field(std::integral_constant<int, 3>());
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            rl[k * BLK + tid] = red[k];
+            hold[k] = red[4 + k];
+        }
+        pendA = pendH = s;
+    }
+    barrier_vm(0);
+    reduce4(pendA, 0);
+    barrier_vm(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rl[k * BLK + tid] = hold[k];
+    barrier_vm(0);
+    reduce4(pendH, 4);
+}
+
 // Sum the block partials of every (geometry, species) into the series at the
 // current time, in a fixed order; then advance the state time.
 template <typename T>
@@ -935,7 +1166,7 @@ struct lbmp_mp {
     int32_t* work;
     int nwork;
     double* setup_tmp;
-    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box
+    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3: LDS DMA (FP32)
     int64_t nblocks;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -1045,6 +1276,11 @@ template <typename T>
 void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     dim3 grid((unsigned)h->nblocks);
+    if (h->variant == 3) {
+        if constexpr (std::is_same<T, float>::value)
+            k_mp_dma<<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+        return;
+    }
     if (h->variant == 2) {
         switch (h->gsz) {
             case 1: k_mp_march<T, 1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->nblocks, h->K, h->ctl); break;
@@ -1143,14 +1379,16 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        if (nread == 3 && (ok01 || ok2)) {
+        const bool ok3 = v == 3 && K == 1 && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32;
+        if (nread == 3 && (ok01 || ok2 || ok3)) {
             h->variant = v;
             h->K = K;
             h->gsz = v == 2 ? gs : std::min(gs, std::max(1, maxS));
             return upload(h);
         }
         return fail(LBMP_EINVAL, "LBMP_TILE must be 'variant,K,species_per_block': variant 0|1 with K 1|2, "
-                                 "or variant 2 with K = z-segment and 1|2|4 species per block");
+                                 "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
+                                 "(FP32 only) with K 1 and at most 64 species per block");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1177,6 +1415,9 @@ lbmp_status autotune(lbmp_mp* h) {
         for (int gs : {1, 2, 4})
             if ((gs <= maxS || gs == 1) && zs <= std::max(8, maxz) && march_fits(h, gs))
                 cand.push_back({zs, gs, 2});
+    if (h->prec == LBMP_FP32)
+        for (int gs : {2, 4, 8, 16, 32, 64})
+            if (gs <= maxS || gs == 2) cand.push_back({1, gs, 3});
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
     LBMP_HIP(hipEventCreate(&e1));
@@ -1354,11 +1595,12 @@ extern "C" lbmp_status mp_workspace_bytes(const lbmp_flow* const* flows, const l
     for (int gi = 0; gi < n_geom; ++gi) {
         if (!flows[gi] || flows[gi]->magic != FLOW_MAGIC) return fail(LBMP_ESTATE, "flow %d is not a valid handle", gi);
         if (species[gi].n_species < 1) return fail(LBMP_EINVAL, "geometry %d: n_species must be >= 1", gi);
-        // fields are addressed with 32-bit byte offsets
-        const int64_t es = precision == LBMP_FP32 ? 4 : 8;
-        if (flows[gi]->N * es > (int64_t)INT32_MAX)
+        // per-node tables are addressed with 32-bit byte offsets, the widest
+        // (the FP64 departure sums) at 8 bytes a node, and the masking offset
+        // must lie beyond every table
+        if (flows[gi]->N * 8 > (int64_t)OOB)
             return fail(LBMP_EINVAL, "geometry %d: %lld nodes exceed the per-field limit of %lld", gi,
-                        (long long)flows[gi]->N, (long long)(INT32_MAX / es));
+                        (long long)flows[gi]->N, (long long)(OOB / 8));
     }
     lbmp_mp* h = make_handle(flows, species, n_geom, precision, max_steps_recorded);
     Carver c(nullptr, ~size_t(0));

@@ -170,12 +170,14 @@ def test_poiseuille_c2_full_length_fp32(lb, pe):
         assert d_err(D[gdir], Dref[gdir], db, 32) < 1e-5, gdir
 
 
-@pytest.mark.parametrize("tile", ["0,1,1", "0,2,3", "1,1,2", "1,2,5", "1,2,8", "2,8,1", "2,3,2", "2,16,4", "2,2,4"])
+@pytest.mark.parametrize("tile", ["0,1,1", "0,2,3", "1,1,2", "1,2,5", "1,2,8", "2,8,1", "2,3,2", "2,16,4", "2,2,4",
+                                  "3,1,1", "3,1,2", "3,1,5"])
 @pytest.mark.parametrize("prec", [64, 32])
 def test_kernel_variants(lb, monkeypatch, tile, prec):
-    """Every step-kernel variant (direct / LDS-staged, K z-planes per thread,
-    species per block) on a ragged porous lattice (nx not a multiple of 64,
-    ny not of 4, nz not of K, species not of the group size) vs the oracle."""
+    """Every step-kernel variant (direct / LDS-staged / z-march / LDS DMA, K
+    z-planes per thread, species per block) on a ragged porous lattice (nx not
+    a multiple of 64, ny not of 4, nz not of K, species not of the group size)
+    vs the oracle. The DMA variant stores FP32 only and refuses FP64."""
     monkeypatch.setenv("LBMP_TILE", tile)
     m = inputs.random_mask(70, 9, 7, 0.3, seed=21)
     u = inputs.random_velocity(m, 0.02, seed=22)
@@ -183,10 +185,15 @@ def test_kernel_variants(lb, monkeypatch, tile, prec):
     kd = np.array([0.1, 0.01, 0.2, 0.5, 0.9])
     T = 150
     flow = lb.lb_flow_from_velocity(m, u)
+    v, K, gs = (int(c) for c in tile.split(","))
+    if v == 3 and prec == 64:
+        with pytest.raises(lb.LbmpError) as e:
+            lb.mp_init(flow, {"D_b": 0.06, "k_a": ka, "k_d": kd}, prec, T)
+        assert e.value.status == -1
+        return
     mp = lb.mp_init(flow, {"D_b": 0.06, "k_a": ka, "k_d": kd}, prec, T)
     st = lb.mp_stats(mp, 0)
-    v, K, gs = (int(c) for c in tile.split(","))
-    assert (st["kernel_variant"], st["tile_k"], st["species_per_block"]) == (v, K, min(gs, 5) if v < 2 else gs)
+    assert (st["kernel_variant"], st["tile_k"], st["species_per_block"]) == (v, K, min(gs, 5) if v != 2 else gs)
     lb.mp_step_n(mp, T)
     out = lb.mp_vacf(mp, 0)
     for s in range(5):
@@ -194,4 +201,27 @@ def test_kernel_variants(lb, monkeypatch, tile, prec):
         Dref = oracle.d_of_t(ref["Z"], ref["V"])
         assert d_err(out["D"][s], Dref, 0.06, prec) < (1e-10 if prec == 64 else 1e-5), s
         assert np.allclose(out["mass"][s], ref["mass"][:, -1], rtol=1e-12 if prec == 64 else 1e-5)
+    mp.free()
+
+
+@pytest.mark.parametrize("gs", [1, 3])
+def test_dma_variant_slit_mixed_waves(lb, monkeypatch, gs):
+    """LDS DMA variant on a slit with flow along x (64 x 8 x 22): waves of the
+    wall-adjacent planes carry sorption, waves of the bulk planes skip it.
+    Three species over 400 FP32 steps vs the full 3D oracle."""
+    monkeypatch.setenv("LBMP_TILE", f"3,1,{gs}")
+    m = inputs.slit_mask(64, 8, 22)
+    u = inputs.random_velocity(m, 0.02, seed=40)
+    ka, kd = np.array([0.02, 0.0, 0.3]), np.array([0.01, 0.2, 0.6])
+    T = 400
+    flow = lb.lb_flow_from_velocity(m, u)
+    mp = lb.mp_init(flow, {"D_b": 0.05, "k_a": ka, "k_d": kd}, 32, T)
+    assert lb.mp_stats(mp, 0)["kernel_variant"] == 3
+    lb.mp_step_n(mp, T)
+    out = lb.mp_vacf(mp, 0)
+    for s in range(3):
+        ref = oracle.vacf(m, u, 0.6, ka[s], kd[s], T)
+        Dref = oracle.d_of_t(ref["Z"], ref["V"])
+        assert d_err(out["D"][s], Dref, 0.05, 32) < 1e-5, s
+        assert np.allclose(out["mass"][s], ref["mass"][:, -1], rtol=1e-5, atol=1e-9)
     mp.free()
