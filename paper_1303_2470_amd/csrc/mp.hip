@@ -57,6 +57,7 @@ struct GeomDev {
     T* Xa;                     // [S][4][NI]
     const T* coef;             // [S][4]
     const T* prob;             // [S][2] = p_a, p_d
+    const double* vmean;       // [S][4]: mean velocity V_0..V_2 of each species (FP64), then unused
     double* part;              // [S][ntile][NRED]
     double* series;            // [Tmax][S][NRED], entry t-1 holds time t
 };
@@ -714,6 +715,7 @@ constexpr int RREG = 3 * RPL;                    // planes z-1, z, z+1
 constexpr int RLD = (RREG + BLK - 1) / BLK;      // region loads per thread and field
 constexpr int STAGE = (RLD + 1) * BLK;           // dwords: region, then adsorbed values
 constexpr int DMA_GMAX = 64;                     // species per block
+constexpr int NSUM = 5;                          // per-node block sums of a species
 
 #define LBMP_LDS(p) ((__attribute__((address_space(3))) void*)(p))
 // s_waitcnt immediate: vmcnt(c), no expcnt wait, lgkmcnt(0)
@@ -735,6 +737,27 @@ __device__ __forceinline__ void barrier_vm(int n) {
     asm volatile("" ::: "memory");
 }
 
+// Lane permutation of an FP64 value (DPP on both halves); lanes without a
+// source receive an unspecified value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Lane 15 of rows 0 and 2 broadcast to rows 1 and 3; rows 0 and 2 receive 0.
+__device__ __forceinline__ double dpp_bcast15(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x142, 0xA, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x142, 0xA, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Read-only tables in the constant address space: uniform loads from it are
+// scalar loads, which do not queue behind the vector-memory traffic.
+using cfloat = const __attribute__((address_space(4))) float;
+
 // Four LDS stages as separate objects, so that the compiler's own tracking of
 // LDS DMA can tell a stage being read from the stages still being filled.
 struct Stages {
@@ -749,8 +772,8 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     __shared__ __align__(16) float st1[STAGE];
     __shared__ __align__(16) float st2[STAGE];
     __shared__ __align__(16) float st3[STAGE];
-    __shared__ __align__(16) double rl[4 * BLK];  // block sums, half of them at a time
-    __shared__ float spt[6 * DMA_GMAX];  // per species of the group: p_a, p_d, c_0..c_3
+    __shared__ __align__(16) double rl[NSUM * BLK];  // per-node sums of a species
+    __shared__ __align__(16) double l2[NRED * 64];   // partial sums of 4 nodes, by series slot
     float* const tag = nullptr;
     const int64_t lb = xcd_remap(blockIdx.x, nblocks);
     const int gi = find_geom(geoms, ngeom, lb);
@@ -770,6 +793,14 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
     const int n = z * plane + (inplane ? y * nx + x : 0);
     const bool act = inplane && G.cls[n] != 0;
+    const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
+    const int64_t ntile = G.ntile;
+    double* const part = G.part;
+    if (!__syncthreads_or(act)) {  // a tile without fluid: zero sums
+        for (int i = tid; i < NRED * (s1 - s0); i += BLK)
+            part[((int64_t)(s0 + i / NRED) * ntile + tile) * NRED + i % NRED] = 0.0;
+        return;
+    }
     const int sl = act ? G.slot[n] : -1;
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
@@ -797,20 +828,13 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     const float* const Xin = (t & 1) ? G.X1 : G.X0;
     float* const Xout = (t & 1) ? G.X0 : G.X1;
     float* const Xa = G.Xa;
-    const float* const coef = G.coef;
-    const float* const prob = G.prob;
-    double* const part = G.part;
-    const int64_t ntile = G.ntile;
-    const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
+    cfloat* const coef = (cfloat*)G.coef;
+    cfloat* const prob = (cfloat*)G.prob;
+    const __attribute__((address_space(4))) double* const vmean =
+        (const __attribute__((address_space(4))) double*)G.vmean;
     const int fb = 4 * s0, fe = 4 * s1;
     const int nL = anyI ? RLD + 1 : RLD, nS = anyI ? 2 : 1;  // per field: DMA loads, stores
     const Stages stg{{st0, st1, st2, st3}};
-    // species constants through LDS: read in the loop as vector loads they
-    // would queue behind the DMA in flight
-    for (int i = tid; i < 6 * (s1 - s0); i += BLK) {
-        const int sp = s0 + i / 6, c = i % 6;
-        spt[i] = c < 2 ? prob[2 * sp + c] : coef[4 * sp + c - 2];
-    }
 
     auto issue = [&](int f, float* stq) {
         const auto rin = mkrsrc(Xin + (int64_t)f * N, (int64_t)N * 4);
@@ -822,32 +846,69 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
                                                      LBMP_LDS(dst + RLD * BLK), 4, offa, 0, 0, 0);
     };
-    // Fixed-order block sums k0..k0+3 of species s from rl: wave w forms sum
-    // k0 + w. The eight sums of a species go through rl in two halves (sums
-    // 0-3 at the species' end, read after the next barrier; sums 4-7 written
-    // after the following barrier and read after the one after that).
-    auto reduce4 = [&](int s, int k0) {
-        const int l = tid & 63;
-        const double* p = rl + wv * BLK + l * 4;
-        double v = ((p[0] + p[1]) + p[2]) + p[3];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    // Block sums of a species in a fixed order, one step per field barrier.
+    // Per node: the drift-corrected VACF terms X_g (a_g - V_g) - V_g X_ads,g
+    // (g = x, y, z; their sum is sum X_g a_g - V_g E_g(t), E_g the stored
+    // total of the first moment), and the mobile and adsorbed density. They
+    // enter rl at the species' end; at q = 1 of the next species wave w folds
+    // sum w, and a quarter of sum 4, into partials of 4 nodes (l2); at q = 0
+    // of the species after that, wave w adds up slots 2w and 2w+1 (2
+    // partials per lane, then over 32 lanes) and stores them: VACF terms in
+    // slots 0-2, mobile density in 3, zeros in 4-6 (the drift term is
+    // already in 0-2), adsorbed density in 7. None of this branches, and the
+    // steps sit where the compiler keeps track of which LDS DMA is in flight
+    // (after a branch, or before the first stage read of a species, it
+    // otherwise waits for all of it). With nothing pending nothing is
+    // stored.
+    const int ln = tid & 63;
+    auto fold = [&]() {
+        // pair (partial of sum w over nodes 4 ln..4 ln+3, partial of sum 4 over
+        // nodes 64 w + 4 (ln % 16) ..+3), one store: a second LDS store in a
+        // row makes the compiler wait for all DMA in flight
+        const double* p = rl + wv * BLK + ln * 4;
+        const double* p4 = rl + 4 * BLK + wv * 64 + (ln & 15) * 4;
+        using d2 = double __attribute__((ext_vector_type(2)));
+        d2 v;
+        v.x = ((p[0] + p[1]) + p[2]) + p[3];
+        v.y = ((p4[0] + p4[1]) + p4[2]) + p4[3];
+        *reinterpret_cast<d2*>(l2 + 2 * (wv * 64 + ln)) = v;
+    };
+    auto finish = [&](int s) {
+        const int k = 2 * wv + (ln >> 5), j = ln & 31;
+        // slots 0-3: partials 2j, 2j+1 of sum k; slot 7: partials 2j, 2j+1
+        // of sum 4 (partial i from wave i / 16, lane i % 16)
+        const int i0 = k < 4 ? 2 * (k * 64 + 2 * j) : 2 * ((j >> 3) * 64 + ((2 * j) & 15)) + 1;
+        double v = l2[i0] + l2[i0 + 2];
+        v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+        v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+        v += dpp_f64<0x124>(v);   // row_ror:4
+        v += dpp_f64<0x128>(v);   // row_ror:8: every lane holds its row's sum
+        v += dpp_bcast15(v);      // rows 1 and 3 add the sum of rows 0 and 2
+        if (k >= 4 && k < 7) v = 0.0;
         // a buffer store: a flat store would also count as LDS traffic and
         // make the next LDS read wait for every DMA in flight
-        bstore(v, mkrsrc(part + (int64_t)s * ntile * NRED, ntile * NRED * 8),
-               l == 0 ? (int)(tile * NRED + k0 + wv) * 8 : OOB);
+        bstore(v, mkrsrc(part + (int64_t)max(s, 0) * ntile * NRED, ntile * NRED * 8),
+               (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
     };
-    double hold[4];  // sums 4-7 of species pendH until they enter rl
 
     issue(fb, st0);
     if (fb + 1 < fe) issue(fb + 1, st1);
     if (fb + 2 < fe) issue(fb + 2, st2);
     const int cb = ly * RX + lx;  // region index of (x-1, y-1) in plane z-1
-    int pendA = -1, pendH = -1, pendB = -1;  // species with sums 0-3 in rl, 4-7 held, 4-7 in rl
+    int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
     for (int s = s0; s < s1; ++s) {
-        double red[NRED];
+        const double pa = (double)prob[2 * s], pd = (double)prob[2 * s + 1];
+        double cq[4], w[3], nv[3];
 #pragma unroll
-        for (int k = 0; k < NRED; ++k) red[k] = 0.0;
+        for (int q = 0; q < 4; ++q) cq[q] = (double)coef[4 * s + q];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            nv[g] = -vmean[4 * s + g];
+            w[g] = act ? (double)av[g] + nv[g] : 0.0;
+        }
+        double red[NSUM];
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
         auto field = [&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int f = 4 * s + q;
@@ -855,27 +916,20 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             // the operations issued after it outstanding: the loads of f+1, f+2
             // and the stores of f-2, f-1
             barrier_vm(nL * (min(f + 2, fe - 1) - f) + nS * (f - max(fb, f - 2)));
-            if constexpr (q == 0) if (pendA >= 0) {
-                reduce4(pendA, 0);
-                pendA = -1;
+            if constexpr (q == 0) {
+                finish(pend2);
+                pend2 = -1;
             }
-            if constexpr (q == 1) if (pendH >= 0) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) rl[k * BLK + tid] = hold[k];
-                pendB = pendH;
-                pendH = -1;
-            }
-            if constexpr (q == 2) if (pendB >= 0) {
-                reduce4(pendB, 4);
-                pendB = -1;
+            if constexpr (q == 1) {
+                fold();
+                pend2 = pend;
+                pend = -1;
             }
             // one live base index: addresses derived from it are not hoisted
             // out of the loop (each would hold a register for the whole loop)
             int c = cb;
             asm volatile("" : "+v"(c));
             const float* sb = stg.at<q>() + c;
-            const float* sp = spt + 6 * (s - s0);
-            const double pa = (double)sp[0], pd = (double)sp[1];
             const double xc = (double)sb[RPL + RX + 1];
             double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
             double xa = 0.0, fa = 0.0, fd = 0.0;
@@ -885,7 +939,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                 fd = pd * xa;              // desorption (Eq. 10)
                 acc0 = (acc0 - fa) + fd;
             }
-            acc0 = __builtin_fma((double)sp[2 + q], src, acc0);
+            acc0 = __builtin_fma(cq[q], src, acc0);
 #pragma unroll
             for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
                 const int o = (1 - lcz(k)) * RPL + (1 - lcy(k)) * RX + (1 - lcx(k));
@@ -897,13 +951,12 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             if (anyI)
                 bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
                        offa);
-            const double xd = act ? xc : 0.0;
             if constexpr (q == 0) {
-                red[3] += xd;
-                red[7] += xa;
+                red[3] += act ? xc : 0.0;
+                red[4] += xa;
             } else {
-                red[q - 1] = __builtin_fma(xd, (double)av[q - 1], red[q - 1]);
-                red[3 + q] += xd + xa;
+                red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
+                if (anyI) red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
             }
             if (f + 3 < fe) issue(f + 3, stg.at<(q + 3) & 3>());
         };
@@ -912,19 +965,15 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
         field(std::integral_constant<int, 2>());
         field(std::integral_constant<int, 3>());
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            rl[k * BLK + tid] = red[k];
-            hold[k] = red[4 + k];
-        }
-        pendA = pendH = s;
+        for (int k = 0; k < NSUM; ++k) rl[k * BLK + tid] = red[k];
+        pend = s;
     }
     barrier_vm(0);
-    reduce4(pendA, 0);
+    finish(pend2);
     barrier_vm(0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) rl[k * BLK + tid] = hold[k];
+    fold();
     barrier_vm(0);
-    reduce4(pendH, 4);
+    finish(pend);
 }
 
 // Sum the block partials of every (geometry, species) into the series at the
@@ -1340,6 +1389,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
         d.coef = (const T*)g.coef; d.prob = (const T*)g.prob;
+        d.vmean = (const double*)g.spc0;
         d.part = g.part; d.series = g.series;
     }
     h->nblocks = blk;
