@@ -712,6 +712,10 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // together. Waves without an interface node skip the sorption arithmetic.
 constexpr int RX = TX + 2, RPL = RX * (TY + 2);  // one haloed plane
 constexpr int RREG = 3 * RPL;                    // planes z-1, z, z+1
+// Region layout: row-interleaved planes, element (hy, pz, hx) at
+// (3 hy + pz) RX + hx, so the 19 stencil values of a node lie within 530
+// dwords of its (x-1, y-1, z-1) corner.
+__host__ __device__ constexpr int region_at(int hy, int pz, int hx) { return (3 * hy + pz) * RX + hx; }
 constexpr int RLD = (RREG + BLK - 1) / BLK;      // region loads per thread and field
 constexpr int STAGE = (RLD + 1) * BLK;           // dwords: region, then adsorbed values
 constexpr int DMA_GMAX = 64;                     // species per block
@@ -810,7 +814,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
     for (int j = 0; j < RLD; ++j) {
         const int e = j * BLK + tid;
-        const int pz = e / RPL, r = e % RPL, hy = r / RX, hx = r % RX;
+        const int hy = e / (3 * RX), pz = (e / RX) % 3, hx = e % RX;
         voff[j] = e < RREG ? (modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx)) * 4
                            : OOB;
     }
@@ -894,7 +898,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     issue(fb, st0);
     if (fb + 1 < fe) issue(fb + 1, st1);
     if (fb + 2 < fe) issue(fb + 2, st2);
-    const int cb = ly * RX + lx;  // region index of (x-1, y-1) in plane z-1
+    const int cb = region_at(ly, 0, lx);  // region index of (x-1, y-1, z-1)
     int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
     for (int s = s0; s < s1; ++s) {
         const double pa = (double)prob[2 * s], pd = (double)prob[2 * s + 1];
@@ -930,34 +934,32 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             int c = cb;
             asm volatile("" : "+v"(c));
             const float* sb = stg.at<q>() + c;
-            const double xc = (double)sb[RPL + RX + 1];
+            // all 19 values first, then the arithmetic
+            float v[NL];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) v[k] = sb[region_at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+            const double xc = (double)sb[region_at(1, 1, 1)];
             double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
-            double xa = 0.0, fa = 0.0, fd = 0.0;
-            if (anyI) {
-                xa = (double)stg.at<q>()[RLD * BLK + tid];
-                fa = isI ? pa * xc : 0.0;  // adsorption (Eq. 9)
-                fd = pd * xa;              // desorption (Eq. 10)
-                acc0 = (acc0 - fa) + fd;
-            }
             acc0 = __builtin_fma(cq[q], src, acc0);
 #pragma unroll
             for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
-                const int o = (1 - lcz(k)) * RPL + (1 - lcy(k)) * RX + (1 - lcx(k));
-                if (k & 1) acc1 = __builtin_fma((double)sb[o], pin[k], acc1);
-                else acc0 = __builtin_fma((double)sb[o], pin[k], acc0);
+                if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
+                else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
             }
+            double nvx = acc0 + acc1;
             const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
-            bstore(sround(acc0 + acc1, r), mkrsrc(Xout + (int64_t)f * N, (int64_t)N * 4), offn);
-            if (anyI)
+            if constexpr (q == 0) red[3] += act ? xc : 0.0;
+            else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
+            if (anyI) {  // wave-uniform: sorption (Eqs. 9, 10) where the wave has interface nodes
+                const double xa = (double)stg.at<q>()[RLD * BLK + tid];
+                const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
+                nvx = (nvx - fa) + fd;
                 bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
                        offa);
-            if constexpr (q == 0) {
-                red[3] += act ? xc : 0.0;
-                red[4] += xa;
-            } else {
-                red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
-                if (anyI) red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
+                if constexpr (q == 0) red[4] += xa;
+                else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
             }
+            bstore(sround(nvx, r), mkrsrc(Xout + (int64_t)f * N, (int64_t)N * 4), offn);
             if (f + 3 < fe) issue(f + 3, stg.at<(q + 3) & 3>());
         };
         field(std::integral_constant<int, 0>());
