@@ -71,6 +71,59 @@ def traffic_record():
     return rec.get("bytes_per_launch")
 
 
+KERNELS = {0: ("direct", "k_mp_step"), 1: ("lds-box", "k_mp_step_box"), 2: ("z-march", "k_mp_march"),
+           3: ("lds-dma", "k_mp_dma")}
+
+
+def rocprof_summary(root: str) -> dict:
+    """Per-kernel summary of rocprofv3 CSV output under `root`: dispatch count
+    and the median per dispatch of its duration and of every counter."""
+    import csv
+    import glob
+    from collections import defaultdict
+    out = {}
+    for f in glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True):
+        out.setdefault("kernel_stats", []).extend(
+            {k: r[k] for k in ("Name", "Calls", "AverageNs", "MinNs", "MaxNs", "Percentage") if k in r}
+            for r in csv.DictReader(open(f)))
+    for f in glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True):
+        d = defaultdict(list)
+        for r in csv.DictReader(open(f)):
+            d[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        out["kernel_trace"] = {k: {"n": len(v), "median_ns": float(np.median(v)), "mean_ns": float(np.mean(v))}
+                               for k, v in d.items()}
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        d = defaultdict(lambda: defaultdict(list))
+        for r in csv.DictReader(open(f)):
+            d[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        cc = out.setdefault("counters", {})
+        for k, v in d.items():
+            cc.setdefault(k, {}).update({c: {"n": len(x), "median": float(np.median(x))} for c, x in v.items()})
+    return out
+
+
+def traffic_from_counters(root: str, copy_bytes: int) -> dict:
+    """HBM bytes per launch of the DMA propagation kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the plain copy of `copy_bytes` bytes in the same directory tree."""
+    summ = rocprof_summary(root)["counters"]
+
+    def pick(name_part, counter):
+        vals = [v[counter]["median"] for k, v in summ.items() if name_part in k and counter in v]
+        return vals[0] if vals else None
+    fk, wk = pick("k_mp_dma", "FETCH_SIZE"), pick("k_mp_dma", "WRITE_SIZE")
+    # the copy kernel: the only other kernel profiled in those runs
+    cf = [v["FETCH_SIZE"]["median"] for k, v in summ.items() if "k_mp" not in k and "FETCH_SIZE" in v]
+    cw = [v["WRITE_SIZE"]["median"] for k, v in summ.items() if "k_mp" not in k and "WRITE_SIZE" in v]
+    f_scale = copy_bytes / (max(cf) * 1024.0)
+    w_scale = copy_bytes / (max(cw) * 1024.0)
+    src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
+    return {"kernel": "k_mp_dma", "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+            "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+            "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale}
+
+
 def cpu_baseline(inputs, steps: int):
     """FP64 oracle on the widest slit of the workload, one species, `steps` steps."""
     import oracle
@@ -101,7 +154,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (known traffic, to scale HBM counters)")
+    ap.add_argument("--rocprof-summary", metavar="DIR", help="only summarise rocprofv3 CSV output under DIR")
+    ap.add_argument("--traffic-record", metavar="DIR",
+                    help="only write profiles/mp_step_traffic.json from FETCH_SIZE / WRITE_SIZE runs of the "
+                         "bench and of --copy-calibration 1024 under DIR")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        print(json.dumps(rocprof_summary(args.rocprof_summary), indent=1))
+        return
+    if args.traffic_record:
+        rec = traffic_from_counters(args.traffic_record, 1024 << 20)
+        with open(os.path.join(ROOT, "profiles", "mp_step_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the batched workload is one GPU's share "
               f"(species/geometry sharding needs no exchange); --gpus {args.gpus} is not supported",
@@ -169,10 +235,11 @@ def main():
                    "lattice_nodes": int(lat_nodes),
                    "lattice_node_species_updates_per_s": lat_nodes * N_SPECIES * args.steps / (tot_ms / 1e3),
                    "tile": {"K": st["tile_k"], "species_per_block": st["species_per_block"],
-                            "variant": "lds-box" if st["kernel_variant"] == 1 else "direct"}},
+                            "variant": KERNELS[st["kernel_variant"]][0]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_mp_step_box" if st["kernel_variant"] == 1 else "k_mp_step", "kernel_avg_ms": k_avg_s * 1e3,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic if st["kernel_variant"] == 3 else None,
+                     "kernel": KERNELS[st["kernel_variant"]][1], "kernel_avg_ms": k_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg},
         "mass_error_max": mass_err,
     }
