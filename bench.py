@@ -57,6 +57,29 @@ def build_workload(lb, inputs):
     return flows, species, nf, ni
 
 
+POROUS_N, POROUS_R, POROUS_PHI, POROUS_SPECIES, POROUS_SEED = 256, 8, 0.4, 16, 2024
+
+
+def build_porous(lb, inputs):
+    """256^3 periodic Boolean sphere pack (R = 8, porosity 0.4), BGK flow solved
+    at a reference force and rescaled to Pe = 10 on the sample length (Stokes
+    regime), 16 species with (k_a, k_d) log-uniform in [1e-4, 1e-1]."""
+    t0 = time.time()
+    mask = inputs.sphere_pack(POROUS_N, POROUS_R, POROUS_PHI, seed=POROUS_SEED)
+    log(f"sphere pack {POROUS_N}^3: {time.time() - t0:.1f}s")
+    t0 = time.time()
+    ref = lb.lb_flow_solve(mask, 1.0, [1e-6, 0.0, 0.0], 1e-6, 200000)
+    u = ref.velocity()
+    ref.free()
+    vbar = float(u[0][mask == 0].mean())
+    u *= (PECLET * D_B / POROUS_N) / vbar
+    fl = lb.lb_flow_from_velocity(mask, u)
+    log(f"flow: {time.time() - t0:.1f}s")
+    ka, kd = inputs.loguniform_rates(POROUS_SPECIES, 1e-4, 1e-1, seed=POROUS_SEED + 2)
+    _, f, n = fl.classes()
+    return [fl], [{"D_b": D_B, "k_a": ka, "k_d": kd}], [f], [n]
+
+
 def traffic_record():
     """Measured HBM bytes per launch of the propagation kernel, if taken on the
     current kernel source (profiles/mp_step_traffic.json)."""
@@ -152,6 +175,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("slits", "porous256"), default="slits",
+                    help="slits: the batched-slit configuration (default); porous256: the 256^3 sphere "
+                         "pack with 16 species (no CPU baseline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (known traffic, to scale HBM counters)")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="only summarise rocprofv3 CSV output under DIR")
@@ -188,7 +214,19 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "launches": 5}))
         return
     lbmp.load_library()
-    flows, species, nf, ni = build_workload(lbmp, inputs)
+    if args.workload == "slits":
+        flows, species, nf, ni = build_workload(lbmp, inputs)
+        n_species = N_SPECIES
+        lat_nodes = sum(NXY * NXY * (W + 2) for W in WIDTHS)
+        workload = ("batched slits W=16,32,48,64 fluid layers x 64x64 lateral, 64 species each (k_a,k_d "
+                    "log-uniform 1e-4..1e-1), D_b=1e-2, Poiseuille Pe=10, FP32 propagation + FP64 sums")
+    else:
+        flows, species, nf, ni = build_porous(lbmp, inputs)
+        n_species = POROUS_SPECIES
+        lat_nodes = POROUS_N ** 3
+        workload = ("256^3 periodic Boolean sphere pack R=8 porosity 0.4, 16 species (k_a,k_d log-uniform "
+                    "1e-4..1e-1), D_b=1e-2, BGK flow at Pe=10, FP32 propagation + FP64 sums")
+        args.no_cpu_baseline = True
     total = args.warmup + args.steps
     t0 = time.time()
     mp = lbmp.mp_init(flows, species, lbmp.LBMP_FP32, total)
@@ -201,18 +239,17 @@ def main():
     # the stream it runs on; the whole sequence bracketed as well
     k_ms, tot_ms = lbmp.mp_profile_steps(mp, args.steps)
     torch.cuda.synchronize()
-    upd_per_step = sum(f * N_SPECIES for f in nf)
+    upd_per_step = sum(f * n_species for f in nf)
     value = upd_per_step * args.steps / (tot_ms / 1e3)
-    lat_nodes = sum(NXY * NXY * (W + 2) for W in WIDTHS)
     # algorithmic bytes per launch: every quantity of every (node, species) read
     # and written once (4 quantities x 4 B x 2), the same for the adsorbed
     # quantities of interfacial nodes, and 16 B of flow data per fluid node
-    alg = sum(N_SPECIES * (32 * f + 32 * n) + 16 * f for f, n in zip(nf, ni))
+    alg = sum(n_species * (32 * f + 32 * n) + 16 * f for f, n in zip(nf, ni))
     k_avg_s = k_ms / 1e3 / args.steps
     achieved = alg / k_avg_s / 1e9
     traffic = traffic_record()
     # accuracy and invariants of this run
-    out = lbmp.mp_vacf(mp, 3, total, 1)
+    out = lbmp.mp_vacf(mp, len(flows) - 1, total, 1)
     mass_err = float(np.abs(out["mass"].sum(axis=1) - 1).max())
     res = {
         "metric": "moment-prop node-species updates/s",
@@ -227,13 +264,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batched slits W=16,32,48,64 fluid layers x 64x64 lateral, "
-                               "64 species each (k_a,k_d log-uniform 1e-4..1e-1), D_b=1e-2, "
-                               "Poiseuille Pe=10, FP32 propagation + FP64 sums",
-                   "geometries": len(WIDTHS), "species_per_geometry": N_SPECIES,
+        "config": {"workload": workload,
+                   "geometries": len(flows), "species_per_geometry": n_species,
                    "fluid_nodes": int(sum(nf)), "interface_nodes": int(sum(ni)),
                    "lattice_nodes": int(lat_nodes),
-                   "lattice_node_species_updates_per_s": lat_nodes * N_SPECIES * args.steps / (tot_ms / 1e3),
+                   "lattice_node_species_updates_per_s": lat_nodes * n_species * args.steps / (tot_ms / 1e3),
                    "tile": {"K": st["tile_k"], "species_per_block": st["species_per_block"],
                             "variant": KERNELS[st["kernel_variant"]][0]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

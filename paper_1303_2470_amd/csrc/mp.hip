@@ -37,6 +37,7 @@ namespace lbmp {
 
 constexpr int BLK = 256;   // threads per block (4 waves)
 constexpr int NRED = 8;    // FP64 sums per (species, step)
+constexpr int KC = 16;     // FP64 constants per species for the DMA kernel
 constexpr int SETUP_RED = 12;
 
 template <typename T>
@@ -57,7 +58,7 @@ struct GeomDev {
     T* Xa;                     // [S][4][NI]
     const T* coef;             // [S][4]
     const T* prob;             // [S][2] = p_a, p_d
-    const double* vmean;       // [S][4]: mean velocity V_0..V_2 of each species (FP64), then unused
+    const double* kc;          // [S][KC]: p_a, p_d, c_0..c_3 (coef), -V_0..-V_2, FP64
     double* part;              // [S][ntile][NRED]
     double* series;            // [Tmax][S][NRED], entry t-1 holds time t
 };
@@ -729,14 +730,17 @@ constexpr int NSUM = 5;                          // per-node block sums of a spe
 // n of its vector-memory operations (which complete in issue order) are
 // outstanding. The empty asm statements keep the compiler from moving memory
 // accesses across it.
-__device__ __forceinline__ void barrier_vm(int n) {
+__device__ __forceinline__ void barrier_vm0() {
     asm volatile("" ::: "memory");
-    if (n >= 16) LBMP_WAIT_VM_LGKM0(16);
-    else if (n >= 14) LBMP_WAIT_VM_LGKM0(14);
-    else if (n >= 12) LBMP_WAIT_VM_LGKM0(12);
-    else if (n >= 10) LBMP_WAIT_VM_LGKM0(10);
-    else if (n >= 5) LBMP_WAIT_VM_LGKM0(5);
-    else LBMP_WAIT_VM_LGKM0(0);
+    LBMP_WAIT_VM_LGKM0(0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+// The same with at most N outstanding; N a constant of the caller.
+template <int N>
+__device__ __forceinline__ void barrier_vm() {
+    asm volatile("" ::: "memory");
+    LBMP_WAIT_VM_LGKM0(N);
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }
@@ -832,23 +836,28 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     const float* const Xin = (t & 1) ? G.X1 : G.X0;
     float* const Xout = (t & 1) ? G.X0 : G.X1;
     float* const Xa = G.Xa;
-    cfloat* const coef = (cfloat*)G.coef;
-    cfloat* const prob = (cfloat*)G.prob;
-    const __attribute__((address_space(4))) double* const vmean =
-        (const __attribute__((address_space(4))) double*)G.vmean;
+    // species constants in FP64, uniform: scalar loads into register pairs
+    const __attribute__((address_space(4))) double* const kc =
+        (const __attribute__((address_space(4))) double*)G.kc;
     const int fb = 4 * s0, fe = 4 * s1;
-    const int nL = anyI ? RLD + 1 : RLD, nS = anyI ? 2 : 1;  // per field: DMA loads, stores
     const Stages stg{{st0, st1, st2, st3}};
 
-    auto issue = [&](int f, float* stq) {
-        const auto rin = mkrsrc(Xin + (int64_t)f * N, (int64_t)N * 4);
+    // field bases advance one field at a time (no per-field 64-bit products)
+    const float* in_f = Xin + (int64_t)fb * N;   // next field to copy into LDS
+    const float* ina_f = Xa + (int64_t)fb * NI;
+    float* out_f = Xout + (int64_t)fb * N;       // field being updated
+    float* outa_f = Xa + (int64_t)fb * NI;
+    auto issue = [&](float* stq) {
+        const auto rin = mkrsrc(in_f, (int64_t)N * 4);
         float* dst = stq + wv * 64;
 #pragma unroll
         for (int j = 0; j < RLD; ++j)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * BLK), 4, voff[j], 0, 0, 0);
         if (anyI)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
-                                                     LBMP_LDS(dst + RLD * BLK), 4, offa, 0, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(ina_f, (int64_t)NI * 4), LBMP_LDS(dst + RLD * BLK), 4,
+                                                     offa, 0, 0, 0);
+        in_f += N;
+        ina_f += NI;
     };
     // Block sums of a species in a fixed order, one step per field barrier.
     // Per node: the drift-corrected VACF terms X_g (a_g - V_g) - V_g X_ads,g
@@ -895,19 +904,19 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
     };
 
-    issue(fb, st0);
-    if (fb + 1 < fe) issue(fb + 1, st1);
-    if (fb + 2 < fe) issue(fb + 2, st2);
+    issue(st0);
+    if (fb + 1 < fe) issue(st1);
+    if (fb + 2 < fe) issue(st2);
     const int cb = region_at(ly, 0, lx);  // region index of (x-1, y-1, z-1)
     int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
     for (int s = s0; s < s1; ++s) {
-        const double pa = (double)prob[2 * s], pd = (double)prob[2 * s + 1];
+        const double pa = kc[KC * s], pd = kc[KC * s + 1];
         double cq[4], w[3], nv[3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cq[q] = (double)coef[4 * s + q];
+        for (int q = 0; q < 4; ++q) cq[q] = kc[KC * s + 2 + q];
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            nv[g] = -vmean[4 * s + g];
+            nv[g] = kc[KC * s + 6 + g];
             w[g] = act ? (double)av[g] + nv[g] : 0.0;
         }
         double red[NSUM];
@@ -918,8 +927,13 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             const int f = 4 * s + q;
             // field f has landed for the whole block once this wave has at most
             // the operations issued after it outstanding: the loads of f+1, f+2
-            // and the stores of f-2, f-1
-            barrier_vm(nL * (min(f + 2, fe - 1) - f) + nS * (f - max(fb, f - 2)));
+            // and the stores of f-2, f-1 (2 (RLD + 1) + 2 * 2 with interface
+            // nodes in the wave, 2 RLD + 2 without); near the ends of the
+            // block's fields, wait for all
+            static_assert(RLD == 5, "wait counts assume 5 region loads per field");
+            if (f - fb < 2 || f + 2 >= fe) barrier_vm0();
+            else if (anyI) barrier_vm<16>();
+            else barrier_vm<12>();
             if constexpr (q == 0) {
                 finish(pend2);
                 pend2 = -1;
@@ -954,13 +968,14 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                 const double xa = (double)stg.at<q>()[RLD * BLK + tid];
                 const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
                 nvx = (nvx - fa) + fd;
-                bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(Xa + (int64_t)f * NI, (int64_t)NI * 4),
-                       offa);
+                bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(outa_f, (int64_t)NI * 4), offa);
                 if constexpr (q == 0) red[4] += xa;
                 else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
             }
-            bstore(sround(nvx, r), mkrsrc(Xout + (int64_t)f * N, (int64_t)N * 4), offn);
-            if (f + 3 < fe) issue(f + 3, stg.at<(q + 3) & 3>());
+            bstore(sround(nvx, r), mkrsrc(out_f, (int64_t)N * 4), offn);
+            out_f += N;
+            outa_f += NI;
+            if (f + 3 < fe) issue(stg.at<(q + 3) & 3>());
         };
         field(std::integral_constant<int, 0>());
         field(std::integral_constant<int, 1>());
@@ -970,11 +985,11 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int k = 0; k < NSUM; ++k) rl[k * BLK + tid] = red[k];
         pend = s;
     }
-    barrier_vm(0);
+    barrier_vm0();
     finish(pend2);
-    barrier_vm(0);
+    barrier_vm0();
     fold();
-    barrier_vm(0);
+    barrier_vm0();
     finish(pend);
 }
 
@@ -1201,7 +1216,7 @@ struct GeomHost {
     int64_t ntile_max;
     // device buffers
     void *pin, *sig, *src, *a, *X0, *X1, *Xa, *coef, *prob;
-    double *part, *series, *spc, *spc0, *zout, *dout;
+    double *part, *series, *spc, *spc0, *kc, *zout, *dout;
 };
 
 }  // namespace lbmp
@@ -1253,6 +1268,7 @@ void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
     g.series = c.take<double>((size_t)std::max<int64_t>(tmax, 1) * S * NRED);
     g.spc = c.take<double>(S * 5);
     g.spc0 = c.take<double>(S * 7);
+    g.kc = c.take<double>(S * KC);
     g.zout = c.take<double>(S * 3 * (tmax + 1));
     g.dout = c.take<double>(S * 3 * (tmax + 1));
 }
@@ -1391,7 +1407,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
         d.coef = (const T*)g.coef; d.prob = (const T*)g.prob;
-        d.vmean = (const double*)g.spc0;
+        d.kc = g.kc;
         d.part = g.part; d.series = g.series;
     }
     h->nblocks = blk;
@@ -1541,6 +1557,7 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     g.min_stay_iface = r[9];
     std::vector<double> spc(S * 5), spc0(S * 7, 0.0);
     std::vector<T> coef(S * 4), prob(S * 2);
+    std::vector<double> kc(S * KC, 0.0);
     g.rho_ref.resize(S);
     g.gam_ref.resize(S);
     g.V.assign(3 * S, 0.0);
@@ -1565,6 +1582,13 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
         for (int k = 0; k < 3; ++k) coef[4 * sp + 1 + k] = (T)(rr * g.V[3 * sp + k]);
         prob[2 * sp] = (T)g.pa[sp];
         prob[2 * sp + 1] = (T)g.pd[sp];
+        kc[KC * sp] = g.pa[sp];
+        kc[KC * sp + 1] = g.pd[sp];
+        kc[KC * sp + 2] = rr;
+        for (int k = 0; k < 3; ++k) {
+            kc[KC * sp + 3 + k] = rr * g.V[3 * sp + k];
+            kc[KC * sp + 6 + k] = -g.V[3 * sp + k];
+        }
         if (g.NI > 0) g.pa_max = std::max(g.pa_max, g.pa[sp]);
     }
     const double min_stay = std::min(g.min_stay_bulk, g.min_stay_iface - g.pa_max);
@@ -1574,6 +1598,7 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     LBMP_HIP(hipMemcpyAsync(g.spc0, spc0.data(), spc0.size() * 8, hipMemcpyHostToDevice, s));
     LBMP_HIP(hipMemcpyAsync(g.coef, coef.data(), coef.size() * sizeof(T), hipMemcpyHostToDevice, s));
     LBMP_HIP(hipMemcpyAsync(g.prob, prob.data(), prob.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.kc, kc.data(), kc.size() * 8, hipMemcpyHostToDevice, s));
     LBMP_HIP(hipStreamSynchronize(s));
     return LBMP_OK;
 }

@@ -126,8 +126,9 @@ def poiseuille_force(peclet: float, d_b: float, width: float, tau: float = 1.0) 
 def random_velocity(mask: np.ndarray, umax: float, seed: int) -> np.ndarray:
     """Random velocity field ``(3, nz, ny, nx)``, zero on solid nodes.
 
-    Only used on tiny lattices to exercise the velocity dependence of the link
-    probabilities; it need not satisfy any flow equation.
+    Exercises the velocity dependence of the link probabilities in tests; it
+    need not satisfy any flow equation (the Eq. 11 start is then not
+    stationary, which exercises the source term).
     """
     rng = np.random.default_rng(seed)
     u = rng.uniform(-umax, umax, size=(3,) + mask.shape)
