@@ -993,19 +993,47 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     finish(pend);
 }
 
-// Sum the block partials of every (geometry, species) into the series at the
-// current time, in a fixed order; then advance the state time.
+// Lattices with many tiles: chunks of RCH tile partials of every
+// (geometry, species) summed by one block each, in a fixed order, into
+// chunk[work][chunk][NRED]; k_mp_reduce then adds the chunks.
+constexpr int RCH = 2048;
+
+template <typename T>
+__global__ void __launch_bounds__(BLK) k_mp_reduce_chunks(const GeomDev<T>* __restrict__ geoms,
+                                                          const int32_t* __restrict__ work, int nch,
+                                                          double* __restrict__ chunk) {
+    __shared__ double lds[NRED * BLK];
+    const int w = blockIdx.x / nch, c = blockIdx.x % nch;
+    const int gi = work[2 * w], s = work[2 * w + 1];
+    const GeomDev<T>& G = geoms[gi];
+    const int64_t ntile = G.ntile;
+    const double* P = G.part + (int64_t)s * ntile * NRED;
+    const int64_t i0 = (int64_t)c * RCH, i1 = min(ntile, i0 + RCH);
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLK)
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) acc[k] += P[i * NRED + k];
+    double r;
+    block_sum8(acc, lds, r);
+    if (threadIdx.x < NRED) chunk[((int64_t)w * nch + c) * NRED + threadIdx.x] = r;
+}
+
+// Sum the block partials (or, with nch > 0, the chunk sums) of every
+// (geometry, species) into the series at the current time, in a fixed order.
 template <typename T>
 __global__ void k_mp_reduce(const GeomDev<T>* __restrict__ geoms, int ngeom,
-                            const int32_t* __restrict__ work, int nwork, Ctl* __restrict__ ctl) {
+                            const int32_t* __restrict__ work, int nwork, int nch,
+                            const double* __restrict__ chunk, Ctl* __restrict__ ctl) {
     const int w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
     const int64_t t = ctl->t;
     if (w < nwork) {
         const int gi = work[2 * w], s = work[2 * w + 1];
         const GeomDev<T>& G = geoms[gi];
-        const int64_t ntile = G.ntile;
-        const double* P = G.part + (int64_t)s * ntile * NRED;
+        const int64_t ntile = nch > 0 ? nch : G.ntile;
+        const double* P = nch > 0 ? chunk + (int64_t)w * nch * NRED : G.part + (int64_t)s * G.ntile * NRED;
         double acc[NRED];
 #pragma unroll
         for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
@@ -1231,6 +1259,8 @@ struct lbmp_mp {
     lbmp::Ctl* ctl;
     int32_t* work;
     int nwork;
+    double* chunk;   // [nwork][nch_max][NRED] chunk sums of the series reduction
+    int nch_max, nch;
     double* setup_tmp;
     int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3: LDS DMA (FP32)
     int64_t nblocks;
@@ -1287,6 +1317,10 @@ lbmp_status carve_all(lbmp_mp* h, Carver& c) {
     h->setup_tmp = c.take<double>(setup);
     h->work = c.take<int32_t>(2 * (size_t)nw);
     h->nwork = nw;
+    int64_t tmx = 1;
+    for (auto& g : h->g) tmx = std::max(tmx, g.ntile_max);
+    h->nch_max = (int)((tmx + RCH - 1) / RCH);
+    h->chunk = c.take<double>((size_t)nw * h->nch_max * NRED);
     return LBMP_OK;
 }
 
@@ -1370,7 +1404,10 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
 template <typename T>
 void launch_step_tail(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
-    k_mp_reduce<T><<<(unsigned)((h->nwork + 3) / 4), 256, 0, s>>>(G, h->ngeom, h->work, h->nwork, h->ctl);
+    if (h->nch > 1)
+        k_mp_reduce_chunks<T><<<(unsigned)(h->nwork * h->nch), BLK, 0, s>>>(G, h->work, h->nch, h->chunk);
+    k_mp_reduce<T><<<(unsigned)((h->nwork + 3) / 4), 256, 0, s>>>(G, h->ngeom, h->work, h->nwork,
+                                                                  h->nch > 1 ? h->nch : 0, h->chunk, h->ctl);
     k_advance<<<1, 64, 0, s>>>(h->ctl);
 }
 
@@ -1411,6 +1448,9 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.part = g.part; d.series = g.series;
     }
     h->nblocks = blk;
+    int64_t tmx = 1;
+    for (const auto& d : v) tmx = std::max(tmx, d.ntile);
+    h->nch = (int)((tmx + RCH - 1) / RCH);  // chunked series reduction when > 1
     LBMP_HIP(hipMemcpyAsync(h->geoms_dev, v.data(), sizeof(GeomDev<T>) * v.size(), hipMemcpyHostToDevice, h->stream));
     LBMP_HIP(hipStreamSynchronize(h->stream));
     return LBMP_OK;

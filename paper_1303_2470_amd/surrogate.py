@@ -228,6 +228,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--save-data", metavar="NPZ", help="write the generated rows (and timings) to NPZ")
+    ap.add_argument("--load-data", metavar="NPZ", help="train and evaluate on rows from NPZ, no generation")
     args = ap.parse_args(argv)
     from . import lbmp
     lbmp.load_library()
@@ -235,29 +237,38 @@ def main(argv=None):
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    t0 = time.time()
-    Xtr, Ytr, gen_s = [], [], 0.0
-    for b in _batches_by_radius(list(range(args.seed, args.seed + args.train_groups)), args.batch):
-        x, y, info = run_groups(lbmp, [group_params(s) for s in b], log)
-        Xtr.append(x)
-        Ytr.append(y)
-    Xtr, Ytr = np.concatenate(Xtr), np.concatenate(Ytr)
-    t_gen = time.time() - t0
+    if args.load_data:
+        d = np.load(args.load_data)
+        Xtr, Ytr, Xte, Yte = d["Xtr"], d["Ytr"], d["Xte"], d["Yte"]
+        t_gen, plain_s, answered = float(d["t_gen"]), float(d["plain_s"]), int(d["answered"])
+        args.train_groups, args.test_groups = int(d["train_groups"]), int(d["test_groups"])
+    else:
+        t0 = time.time()
+        Xtr, Ytr = [], []
+        for b in _batches_by_radius(list(range(args.seed, args.seed + args.train_groups)), args.batch):
+            x, y, info = run_groups(lbmp, [group_params(s) for s in b], log)
+            Xtr.append(x)
+            Ytr.append(y)
+        Xtr, Ytr = np.concatenate(Xtr), np.concatenate(Ytr)
+        t_gen = time.time() - t0
+        # held-out media: new seeds; the plain method is timed on them
+        Xte, Yte, plain_s, answered = [], [], 0.0, 0
+        test_seeds = list(range(10 ** 6 + args.seed, 10 ** 6 + args.seed + args.test_groups))
+        for b in _batches_by_radius(test_seeds, args.batch):
+            ts = time.time()
+            x, y, info = run_groups(lbmp, [group_params(s) for s in b], log)
+            plain_s += time.time() - ts
+            Xte.append(x)
+            Yte.append(y)
+            answered += len(y)
+        Xte, Yte = np.concatenate(Xte), np.concatenate(Yte)
+        if args.save_data:
+            np.savez(args.save_data, Xtr=Xtr, Ytr=Ytr, Xte=Xte, Yte=Yte, t_gen=t_gen, plain_s=plain_s,
+                     answered=answered, train_groups=args.train_groups, test_groups=args.test_groups)
     t1 = time.time()
     sg, losses = train(lbmp, Xtr, Ytr, epochs=args.epochs, seed=args.seed, log=log)
     sg.sync()
     t_train = time.time() - t1
-    # held-out media: new seeds; the plain method is timed on them
-    Xte, Yte, plain_s, answered = [], [], 0.0, 0
-    test_seeds = list(range(10 ** 6 + args.seed, 10 ** 6 + args.seed + args.test_groups))
-    for b in _batches_by_radius(test_seeds, args.batch):
-        ts = time.time()
-        x, y, info = run_groups(lbmp, [group_params(s) for s in b], log)
-        plain_s += time.time() - ts
-        Xte.append(x)
-        Yte.append(y)
-        answered += len(y)
-    Xte, Yte = np.concatenate(Xte), np.concatenate(Yte)
     ev = evaluate(sg, Xte, Yte)
     import torch
     xt = torch.tensor(Xte, dtype=torch.float32, device="cuda")
