@@ -4,6 +4,7 @@ import math
 import os
 
 import numpy as np
+import pytest
 
 from paper_1303_2470_amd import inputs
 
@@ -41,3 +42,15 @@ def test_poiseuille_force_recipe():
     # g = 12 nu vbar / L^2 with nu = 1/6 at tau = 1
     g = inputs.poiseuille_force(10.0, 0.01, 64)
     assert abs(g - 12 * (1 / 6) * (10 * 0.01 / 64) / 64 ** 2) < 1e-20
+
+
+def test_fcc_rates_invert_the_equilibrium_share():
+    """k_a from f_a (fcc workload) reproduces f_a through the Eq. 11 weights."""
+    from paper_1303_2470_amd import fcc
+    nf, ni, kd = 260000, 60000, 1e-2
+    f = np.array([0.0, 0.3, 0.79, 0.97])
+    ka = fcc.adsorption_rates(f, nf, ni, kd)
+    share = ni * ka / kd / (nf + ni * ka / kd)
+    assert np.allclose(share, f, rtol=1e-13, atol=0)
+    with pytest.raises(ValueError):
+        fcc.adsorption_rates([1.0], nf, ni, kd)
