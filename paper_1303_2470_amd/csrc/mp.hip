@@ -815,12 +815,15 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     const int offn = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
     // this thread's share of the stencil region, element e = j * BLK + tid
     int voff[RLD];
+    // (solid nodes hold zero fields and are never written: their elements are
+    // masked like the padding, so the copy fetches fluid nodes only and the
+    // out-of-range lanes write the same zeros)
 #pragma unroll
     for (int j = 0; j < RLD; ++j) {
         const int e = j * BLK + tid;
         const int hy = e / (3 * RX), pz = (e / RX) % 3, hx = e % RX;
-        voff[j] = e < RREG ? (modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx)) * 4
-                           : OOB;
+        const int m = e < RREG ? modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
+        voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
     }
     double pin[NL];
 #pragma unroll
