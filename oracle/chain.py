@@ -75,13 +75,11 @@ def stationary_weights(mask, pa, pd, nbhd=18):
     return w / w.sum()
 
 
-def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18):
-    """Z_g(m), m = 0..steps, from the explicit transition matrix.
-
-    Z(0) = E[v(0)^2]; Z(m >= 1) = pi0^T B M^(m-1) b, where M is the transition
-    matrix, B the displacement-weighted transition matrix and b = B 1.
-    Returns (Z (3, steps+1), V (3,)).
-    """
+def transition_matrix(mask, u, lam, pa, pd, nbhd=18):
+    """The tracer chain on the states "mobile at a fluid node" (first N_F) and
+    "adsorbed at an interfacial node" (next N_I), built link by link: M the
+    transition matrix, B[g] its displacement-weighted version, C2[g] the
+    conditional E[v_g^2 | state]. Returns (M, B, C2, n_fluid)."""
     mask = np.asarray(mask).astype(bool)
     nz, ny, nx = mask.shape
     fluid, iface = _states(mask, nbhd)
@@ -117,6 +115,17 @@ def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18):
         s = ads[int(n)]
         M[s, mob[int(n)]] += pd
         M[s, s] += 1.0 - pd
+    return M, B, C2, nf
+
+
+def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18):
+    """Z_g(m), m = 0..steps, from the explicit transition matrix.
+
+    Z(0) = E[v(0)^2]; Z(m >= 1) = pi0^T B M^(m-1) b, where M is the transition
+    matrix, B the displacement-weighted transition matrix and b = B 1.
+    Returns (Z (3, steps+1), V (3,)).
+    """
+    M, B, C2, nf = transition_matrix(mask, u, lam, pa, pd, nbhd)
     pi0 = stationary_weights(mask, pa, pd, nbhd)
     b = B.sum(axis=2)
     V = pi0 @ b.T
@@ -128,6 +137,19 @@ def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18):
             Z[g, m] = row @ b[g]
             row = row @ M
     return Z, V
+
+
+def dense_chain_uptake(mask, u, lam, pa, pd, steps, nbhd=18):
+    """Mobile and adsorbed probability for t = 0..steps of the chain started
+    uniformly on the mobile states (p_d = 0 allowed): pi_t = pi_0 M^t."""
+    M, _, _, nf = transition_matrix(mask, u, lam, pa, pd, nbhd)
+    pi = np.zeros(M.shape[0])
+    pi[:nf] = 1.0 / nf
+    mob, ads = np.zeros(steps + 1), np.zeros(steps + 1)
+    for t in range(steps + 1):
+        mob[t], ads[t] = pi[:nf].sum(), pi[nf:].sum()
+        pi = pi @ M
+    return mob, ads
 
 
 def walkers(mask, u, lam, pa, pd, steps, n_walkers, seed, nbhd=18):

@@ -51,9 +51,11 @@ def _load():
                              c_long, c_int, _dp, _dp, _dp, _dp]
     lib.orc_bgk.argtypes = [c_int, c_int, c_int, _u8, c_double, _dp, c_double, c_long, c_int,
                             _dp, _dp, ctypes.POINTER(c_long), ctypes.POINTER(c_double)]
+    lib.orc_uptake.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, c_double, c_double, c_int,
+                               c_long, _dp, _dp]
     lib.orc_threads.argtypes = []
     for f in ("orc_classify", "orc_links", "orc_step", "orc_propagate", "orc_vacf", "orc_bgk",
-              "orc_threads"):
+              "orc_uptake", "orc_threads"):
         getattr(lib, f).restype = c_int
     _lib = lib
     return lib
@@ -135,6 +137,19 @@ def vacf(mask, u, lam: float, pa: float, pd: float, steps: int, qmask: int = 15,
         raise ValueError("oracle rejected the input (no fluid node, or p_d <= 0)")
     return {"Z": Z.reshape(3, T1), "V": V, "mass": mass.reshape(2, T1),
             "mom": mom.reshape(3, T1)}
+
+
+def uptake(mask, u, lam: float, pa: float, pd: float, steps: int, nbhd: int = 18) -> dict:
+    """Out-of-equilibrium density propagation (Eqs. 7, 9, 10 with the density
+    as the propagated quantity): uniform mobile start 1/N_F, nothing adsorbed;
+    p_d = 0 allowed. Returns the mobile and adsorbed totals for t = 0..steps."""
+    m, nx, ny, nz = _mask(mask)
+    ua, up = _vel(u, m.shape)
+    mob = np.zeros(steps + 1)
+    ads = np.zeros(steps + 1)
+    if _load().orc_uptake(nx, ny, nz, m, up, lam, pa, pd, nbhd, steps, mob, ads) != 0:
+        raise ValueError("oracle rejected the input (no fluid node)")
+    return {"mobile": mob, "adsorbed": ads}
 
 
 def d_of_t(Z: np.ndarray, V: np.ndarray) -> np.ndarray:

@@ -180,6 +180,41 @@ int orc_propagate(int nx, int ny, int nz, const uint8_t* solid, const double* u,
     return 0;
 }
 
+/* ---- Uptake out of equilibrium (density propagated; Eqs. 7, 9, 10) ------ */
+/* The density as the propagated quantity, from a uniform mobile density
+ * 1/N_F on the fluid nodes and no adsorbed density; p_d = 0 (irreversible
+ * adsorption) is allowed. Outputs, for t = 0..T: mobile[t] and adsorbed[t],
+ * the total mobile and adsorbed densities. Returns -1 when the lattice has no
+ * fluid node. */
+int orc_uptake(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+               double lambda, double pa, double pd, int nbhd, long T,
+               double* mobile, double* adsorbed)
+{
+    long N = (long)nx * ny * nz;
+    int8_t* cls = (int8_t*)malloc(N);
+    double* p = (double*)malloc(sizeof(double) * Q19 * N);
+    double* X = (double*)malloc(sizeof(double) * N);
+    double* Xa = (double*)malloc(sizeof(double) * N);
+    double* Y = (double*)malloc(sizeof(double) * N);
+    double* Ya = (double*)malloc(sizeof(double) * N);
+    orc_classify(nx, ny, nz, solid, nbhd, cls);
+    orc_links(nx, ny, nz, solid, u, lambda, p);
+    long nf = 0;
+    for (long n = 0; n < N; ++n) nf += cls[n] != 0;
+    if (nf == 0) { free(cls); free(p); free(X); free(Xa); free(Y); free(Ya); return -1; }
+    for (long n = 0; n < N; ++n) { X[n] = cls[n] != 0 ? 1.0 / (double)nf : 0.0; Xa[n] = 0.0; }
+    for (long t = 0; t <= T; ++t) {
+        mobile[t] = nsum(X, N);
+        adsorbed[t] = nsum(Xa, N);
+        if (t == T) break;
+        orc_step(nx, ny, nz, cls, p, pa, pd, X, Xa, Y, Ya);
+        memcpy(X, Y, sizeof(double) * N);
+        memcpy(Xa, Ya, sizeof(double) * N);
+    }
+    free(cls); free(p); free(X); free(Xa); free(Y); free(Ya);
+    return 0;
+}
+
 /* ---- VACF by moment propagation (Eqs. 5, 11, 12) ------------------------ */
 /* Outputs, for t = 0..T:
  *   Z[g*(T+1) + t]   velocity autocorrelation in direction g (x, y, z);

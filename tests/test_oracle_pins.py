@@ -298,3 +298,33 @@ def test_taylor_aris_with_sorption_eq15(orc, pe):
     K = orc.d_of_t(r["Z"], r["V"])[0, -1]
     ex = closed_forms.taylor_aris_k(pe_true, ka, kd, L, db)
     assert abs(K / db / ex - 1) < 0.015
+
+
+# ---------------------------------------------------------------- uptake (out of equilibrium)
+@pytest.mark.parametrize("pa,pd", [(0.05, 0.0), (0.08, 0.02)])
+def test_uptake_two_layer_slit_closed_form(orc, pa, pd):
+    """Two fluid layers between walls: every fluid node is interfacial and, at
+    rest, a uniform density stays uniform (detailed balance of Eq. 8), so each
+    node is the two-state chain: mobile m(t) = m_eq + (1 - m_eq)(1 - p_a - p_d)^t,
+    m_eq = p_d / (p_a + p_d) (m(t) = (1 - p_a)^t for irreversible adsorption)."""
+    m = inputs.slit_mask(5, 4, 4)
+    T = 60
+    r = orc.uptake(m, None, 0.3, pa, pd, T)
+    t = np.arange(T + 1)
+    meq = pd / (pa + pd)
+    ref = meq + (1 - meq) * (1 - pa - pd) ** t
+    assert np.abs(r["mobile"] - ref).max() < 1e-14
+    assert np.abs(r["mobile"] + r["adsorbed"] - 1).max() < 1e-14
+
+
+@pytest.mark.parametrize("pd", [0.0, 0.03])
+def test_uptake_matches_dense_chain(orc, pd):
+    """Random porous lattice with a random velocity field vs pi_0 M^t."""
+    from oracle import chain
+    m = inputs.random_mask(6, 5, 4, 0.3, seed=17)
+    u = inputs.random_velocity(m, 0.02, seed=18)
+    T = 40
+    r = orc.uptake(m, u, 0.7, 0.06, pd, T)
+    mob, ads = chain.dense_chain_uptake(m, u, 0.7, 0.06, pd, T)
+    assert np.abs(r["mobile"] - mob).max() < 1e-13
+    assert np.abs(r["adsorbed"] - ads).max() < 1e-13
