@@ -156,6 +156,30 @@ lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* Z, 
 /* Steps done so far (0 right after mp_init). */
 lbmp_status mp_steps_done(const lbmp_mp* h, int64_t* t);
 
+/*
+ * Out-of-equilibrium uptake (the outlook of the paper's conclusion: the
+ * density as the propagated quantity of Eqs. 7, 9 and 10, irreversible
+ * adsorption k_d = 0 allowed). Arguments as for mp_init, except that k_d may
+ * be 0; every species starts at tau = 0 from the density 1/N_F on every fluid
+ * node with nothing adsorbed. mp_step_n advances it; the handle records the
+ * total mobile and adsorbed density of every species at every step and no
+ * VACF (mp_vacf returns LBMP_ESTATE). Densities are stored as they are (no
+ * reference weights), in FP32 with stochastic rounding or in FP64.
+ */
+lbmp_status mp_uptake_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
+                           int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
+                           void* hip_stream, lbmp_mp** out);
+/*
+ * Synchronises the stream and returns, for geometry `geom` and
+ * tau = t0 .. t0+count-1 (tau < steps done: the totals of a state are
+ * recorded by the step that reads it):
+ *  mobile[s*count + k], adsorbed[s*count + k]  total mobile and adsorbed
+ *  density of species s at tau = t0 + k.
+ * Either pointer may be NULL. LBMP_ESTATE for a handle made by mp_init,
+ * LBMP_EINVAL for times not recorded, LBMP_ENUMERIC for a non-finite total.
+ */
+lbmp_status mp_uptake(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* mobile, double* adsorbed);
+
 typedef struct {
     int64_t n_nodes, n_fluid, n_iface;
     double lambda;

@@ -1195,6 +1195,15 @@ __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __re
     }
 }
 
+// Uptake start: density 1/N_F on every fluid node (the first-moment fields of
+// each species stay zero).
+template <typename T>
+__global__ void k_init_uptake(const int8_t* __restrict__ cls, int64_t N, double rho0, T* __restrict__ X) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (n < N) X[(int64_t)(4 * s) * N + n] = cls[n] != 0 ? (T)rho0 : T(0);
+}
+
 // Time series of Z_g and D_g (discrete Eq. 3 about the mean drift) for one
 // geometry, one thread per (species, direction), compensated summation.
 // Z(t) = V^2 + sum_r dP a - E(t) V, where E(t) = sum dP + sum dP_ads is the
@@ -1266,6 +1275,7 @@ struct lbmp_mp {
     int nch_max, nch;
     double* setup_tmp;
     int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3: LDS DMA (FP32)
+    int uptake;           // out-of-equilibrium density propagation (no VACF)
     int64_t nblocks;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -1340,15 +1350,17 @@ lbmp_status resolve_lambda(const lbmp_species& sp, double* lam) {
     return LBMP_OK;
 }
 
-lbmp_status validate_species(const lbmp_species& sp, int gi) {
+lbmp_status validate_species(const lbmp_species& sp, int gi, bool uptake) {
     if (sp.n_species < 1) return fail(LBMP_EINVAL, "geometry %d: n_species must be >= 1", gi);
     if (!sp.k_a || !sp.k_d) return fail(LBMP_EINVAL, "geometry %d: rate arrays are NULL", gi);
     for (int s = 0; s < sp.n_species; ++s) {
         if (!(sp.k_a[s] >= 0.0) || !std::isfinite(sp.k_a[s]))
             return fail(LBMP_EINVAL, "geometry %d: k_a[%d] must be finite and >= 0", gi, s);
-        if (!(sp.k_d[s] > 0.0 && sp.k_d[s] <= 1.0))
+        if (uptake ? !(sp.k_d[s] >= 0.0 && sp.k_d[s] <= 1.0) : !(sp.k_d[s] > 0.0 && sp.k_d[s] <= 1.0))
             return fail(LBMP_EINVAL,
-                        "geometry %d: k_d[%d] must be in (0, 1] (irreversible sorption has no equilibrium VACF)",
+                        uptake ? "geometry %d: k_d[%d] must be in [0, 1]"
+                               : "geometry %d: k_d[%d] must be in (0, 1] (irreversible sorption has no "
+                                 "equilibrium VACF; use the uptake calls)",
                         gi, s);
     }
     double lam;
@@ -1607,9 +1619,10 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     g.Z0.assign(3 * S, 0.0);
     g.pa_max = 0.0;
     for (int sp = 0; sp < S; ++sp) {
-        const double Kr = g.pa[sp] / g.pd[sp];
+        // uptake mode stores absolute densities (no reference, no source)
+        const double Kr = h->uptake ? 0.0 : g.pa[sp] / g.pd[sp];
         const double Zp = (double)g.nf + (double)g.NI * Kr;
-        const double rr = 1.0 / Zp, gr = Kr / Zp;
+        const double rr = h->uptake ? 0.0 : 1.0 / Zp, gr = Kr / Zp;
         g.rho_ref[sp] = rr;
         g.gam_ref[sp] = gr;
         spc[5 * sp] = rr;
@@ -1646,13 +1659,23 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     return LBMP_OK;
 }
 
-// The state at t = 1 lives in the odd buffer X1; X0 starts at zero.
+// The state at t = 1 lives in the odd buffer X1; X0 starts at zero. In uptake
+// mode X1 holds the start tau = 0: density 1/N_F on every fluid node, first
+// moments and adsorbed densities zero.
 template <typename T>
 lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
     const int64_t N = g.N;
     double* b64 = h->setup_tmp + 18 * N;
     double* src64 = b64 + 3 * N;
     LBMP_HIP(hipMemsetAsync(g.X0, 0, (size_t)g.S * 4 * N * sizeof(T), s));
+    if (h->uptake) {
+        LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * N * sizeof(T), s));
+        LBMP_HIP(hipMemsetAsync(g.Xa, 0, (size_t)g.S * 4 * std::max<int64_t>(g.NI, 1) * sizeof(T), s));
+        dim3 grid((unsigned)((N + BLK - 1) / BLK), (unsigned)g.S);
+        k_init_uptake<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, N, 1.0 / (double)g.nf, (T*)g.X1);
+        LBMP_HIP(hipGetLastError());
+        return LBMP_OK;
+    }
     dim3 grid((unsigned)((std::max<int64_t>(N, g.NI) + BLK - 1) / BLK), (unsigned)g.S);
     k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64,
                                          (T*)g.X1, (T*)g.Xa);
@@ -1730,9 +1753,10 @@ extern "C" lbmp_status mp_workspace_bytes(const lbmp_flow* const* flows, const l
     return LBMP_OK;
 }
 
-extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
-                               int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
-                               void* hip_stream, lbmp_mp** out) {
+namespace {
+lbmp_status mp_create(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom, int precision,
+                      int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes, void* hip_stream, bool uptake,
+                      lbmp_mp** out) {
     if (!out) return fail(LBMP_EINVAL, "out is NULL");
     *out = nullptr;
     size_t need = 0;
@@ -1740,11 +1764,12 @@ extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species
     if (st != LBMP_OK) return st;
     if (!dev_ws || ws_bytes < need) return fail(LBMP_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
     for (int gi = 0; gi < n_geom; ++gi) {
-        st = validate_species(species[gi], gi);
+        st = validate_species(species[gi], gi, uptake);
         if (st != LBMP_OK) return st;
     }
     lbmp_mp* h = make_handle(flows, species, n_geom, precision, max_steps_recorded);
     h->stream = static_cast<hipStream_t>(hip_stream);
+    h->uptake = uptake ? 1 : 0;
     for (int gi = 0; gi < n_geom; ++gi) {
         GeomHost& g = h->g[gi];
         resolve_lambda(species[gi], &g.lam);
@@ -1763,6 +1788,48 @@ extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species
         return st;
     }
     *out = h;
+    return LBMP_OK;
+}
+}  // namespace
+
+extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
+                               int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
+                               void* hip_stream, lbmp_mp** out) {
+    return mp_create(flows, species, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream, false,
+                     out);
+}
+
+extern "C" lbmp_status mp_uptake_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
+                                      int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
+                                      void* hip_stream, lbmp_mp** out) {
+    return mp_create(flows, species, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream, true,
+                     out);
+}
+
+extern "C" lbmp_status mp_uptake(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* mobile,
+                                 double* adsorbed) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (!h->uptake) return fail(LBMP_ESTATE, "not an uptake handle (made by mp_init)");
+    if (geom < 0 || geom >= h->ngeom) return fail(LBMP_EINVAL, "geometry index %d out of range", geom);
+    // the sums of the state at tau are recorded by the step that reads it
+    if (t0 < 0 || count < 0 || t0 + count > h->steps)
+        return fail(LBMP_EINVAL, "times %lld..%lld not recorded (0..%lld)", (long long)t0,
+                    (long long)(t0 + count - 1), (long long)(h->steps - 1));
+    GeomHost& g = h->g[geom];
+    const int S = g.S;
+    std::vector<double> ser((size_t)count * S * NRED);
+    if (count > 0)
+        LBMP_HIP(hipMemcpyAsync(ser.data(), g.series + t0 * S * NRED, ser.size() * 8, hipMemcpyDeviceToHost,
+                                h->stream));
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    for (int sp = 0; sp < S; ++sp)
+        for (int64_t i = 0; i < count; ++i) {
+            if (mobile) mobile[sp * count + i] = ser[(i * S + sp) * NRED + 3];
+            if (adsorbed) adsorbed[sp * count + i] = ser[(i * S + sp) * NRED + 7];
+        }
+    for (size_t i = 0; i < ser.size(); ++i)
+        if (!std::isfinite(ser[i])) return fail(LBMP_ENUMERIC, "non-finite value in the recorded totals");
     return LBMP_OK;
 }
 
@@ -1806,6 +1873,7 @@ extern "C" lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, 
                                double* mass, double* vbar) {
     lbmp_status st = check_mp(h);
     if (st != LBMP_OK) return st;
+    if (h->uptake) return fail(LBMP_ESTATE, "an uptake handle records totals only (mp_uptake)");
     if (geom < 0 || geom >= h->ngeom) return fail(LBMP_EINVAL, "geometry index %d out of range", geom);
     if (t0 < 0 || count < 0 || t0 + count - 1 > h->steps)
         return fail(LBMP_EINVAL, "times %lld..%lld not recorded (0..%lld)", (long long)t0,

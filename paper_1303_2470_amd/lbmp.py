@@ -50,6 +50,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["lbmp_last_error", "lbmp_version", "lb_flow_workspace_bytes", "lb_flow_solve",
            "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
            "mp_workspace_bytes", "mp_init", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
+           "mp_uptake_init", "mp_uptake",
            "mp_state", "mp_profile_steps", "mp_free", "sg_param_count", "sg_workspace_bytes",
            "sg_create", "sg_set_params", "sg_get_params", "sg_set_normalization", "sg_train_step",
            "sg_gradients", "sg_predict", "sg_sync", "sg_free"]
@@ -88,6 +89,8 @@ def load_library(path: str = LIB_PATH):
         "mp_init": ([P(vp), P(Species), i32, i32, i64, vp, sz, vp, P(vp)], i32),
         "mp_step_n": ([vp, i64], i32),
         "mp_vacf": ([vp, i32, i64, i64, vp, vp, vp, vp], i32),
+        "mp_uptake_init": ([P(vp), P(Species), i32, i32, i64, vp, sz, vp, P(vp)], i32),
+        "mp_uptake": ([vp, i32, i64, i64, vp, vp], i32),
         "mp_steps_done": ([vp, P(i64)], i32),
         "mp_stats": ([vp, i32, P(Stats)], i32),
         "mp_state": ([vp, i32, i32, vp, vp], i32),
@@ -248,7 +251,8 @@ class MP:
             pass
 
 
-def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stream=None) -> MP:
+def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stream=None,
+            _entry: str = "mp_init") -> MP:
     """Set up moment propagation for flows[g] with species[g] = dict(D_b= or Delta=, k_a=, k_d=)."""
     torch = _torch_cuda()
     load_library()
@@ -271,9 +275,25 @@ def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stre
     ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
     stream = stream or torch.cuda.Stream()
     h = ctypes.c_void_p()
-    _check(_lib.mp_init(fl, sps, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()), nb.value,
-                        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+    _check(getattr(_lib, _entry)(fl, sps, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
     return MP(h, ws, list(flows), [int(s.n_species) for s in sps], stream, keep)
+
+
+def mp_uptake_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stream=None) -> MP:
+    """Out-of-equilibrium uptake: uniform mobile start, k_d = 0 allowed."""
+    return mp_init(flows, species, precision, max_steps, stream, _entry="mp_uptake_init")
+
+
+def mp_uptake(mp: MP, geom: int = 0, t0: int = 0, count: int | None = None) -> dict:
+    """mobile, adsorbed (S, count) totals for tau = t0..t0+count-1."""
+    S = mp.n_species[geom]
+    if count is None:
+        count = mp_steps_done(mp) - t0
+    mob = np.zeros((S, count))
+    ads = np.zeros((S, count))
+    _check(_lib.mp_uptake(mp.handle, geom, t0, count, _ptr(mob), _ptr(ads)))
+    return {"mobile": mob, "adsorbed": ads}
 
 
 def mp_step_n(mp: MP, n: int):

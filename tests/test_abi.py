@@ -75,6 +75,8 @@ def test_host_validation_errors(lib):
     # bad handles
     assert lib.mp_step_n(None, 1) == -6
     assert lib.lb_flow_velocity(None, None) == -6
+    assert lib.mp_uptake(None, 0, 0, 1, None, None) == -6
+    assert lib.mp_uptake_init(None, None, 1, 32, 10, None, 0, None, None) == -1
     # invalid interface rule
     g, m = _geom(lbmp, inputs.slit_mask(4, 4, 8), nb=7)
     assert lib.lb_flow_solve(ctypes.byref(g), 1.0, f, 1e-10, 10, 100, None, 0, None, 0, None,
