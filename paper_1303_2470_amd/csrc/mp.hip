@@ -842,25 +842,25 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     // species constants in FP64, uniform: scalar loads into register pairs
     const __attribute__((address_space(4))) double* const kc =
         (const __attribute__((address_space(4))) double*)G.kc;
-    const int fb = 4 * s0, fe = 4 * s1;
     const Stages stg{{st0, st1, st2, st3}};
 
-    // field bases advance one field at a time (no per-field 64-bit products)
-    const float* in_f = Xin + (int64_t)fb * N;   // next field to copy into LDS
-    const float* ina_f = Xa + (int64_t)fb * NI;
-    float* out_f = Xout + (int64_t)fb * N;       // field being updated
-    float* outa_f = Xa + (int64_t)fb * NI;
-    auto issue = [&](float* stq) {
-        const auto rin = mkrsrc(in_f, (int64_t)N * 4);
-        float* dst = stq + wv * 64;
+    // Buffer resources span the 4 fields of one species; the field of quantity
+    // q sits at soffset q * (bytes per field). A masked offset (OOB) lies
+    // beyond the 4 fields whether or not the hardware adds soffset before the
+    // range check, and OOB + 3 fields does not wrap (the host keeps 16 N and
+    // 16 N_I below OOB for this kernel).
+    const int NB = N * 4, NIB = NI * 4;
+    const int64_t sN = 4 * (int64_t)N, sNI = 4 * (int64_t)NI;
+    auto issue = [&](auto qpc, auto anyc, const float* ib, const float* iab) {
+        constexpr int qp = decltype(qpc)::value;  // quantity (and stage) of the copied field
+        const auto rin = mkrsrc(ib, 4 * (int64_t)NB);
+        float* dst = stg.at<qp>() + wv * 64;
 #pragma unroll
         for (int j = 0; j < RLD; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * BLK), 4, voff[j], 0, 0, 0);
-        if (anyI)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(ina_f, (int64_t)NI * 4), LBMP_LDS(dst + RLD * BLK), 4,
-                                                     offa, 0, 0, 0);
-        in_f += N;
-        ina_f += NI;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * BLK), 4, voff[j], qp * NB, 0, 0);
+        if constexpr (decltype(anyc)::value)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(iab, 4 * (int64_t)NIB), LBMP_LDS(dst + RLD * BLK), 4,
+                                                     offa, qp * NIB, 0, 0);
     };
     // Block sums of a species in a fixed order, one step per field barrier.
     // Per node: the drift-corrected VACF terms X_g (a_g - V_g) - V_g X_ads,g
@@ -907,87 +907,122 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
     };
 
-    issue(st0);
-    if (fb + 1 < fe) issue(st1);
-    if (fb + 2 < fe) issue(st2);
     const int cb = region_at(ly, 0, lx);  // region index of (x-1, y-1, z-1)
     int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
-    for (int s = s0; s < s1; ++s) {
-        const double pa = kc[KC * s], pd = kc[KC * s + 1];
-        double cq[4], w[3], nv[3];
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    // anyc: the wave has interface nodes (wave-uniform; both paths pass the
+    // same barriers). firstc / lastc: the block's first / last species, whose
+    // first / last two fields wait for every copy in flight (fewer operations
+    // follow their copies than the steady-state wait counts assume).
+    auto run = [&](auto anyc) {
+        constexpr bool ANYI = decltype(anyc)::value;
+        const float* in_s = Xin + (int64_t)s0 * sN;  // species s of the input fields
+        const float* ina_s = Xa + (int64_t)s0 * sNI;
+        float* out_s = Xout + (int64_t)s0 * sN;
+        float* outa_s = Xa + (int64_t)s0 * sNI;
+        issue(std::integral_constant<int, 0>(), anyc, in_s, ina_s);
+        issue(std::integral_constant<int, 1>(), anyc, in_s, ina_s);
+        issue(std::integral_constant<int, 2>(), anyc, in_s, ina_s);
+        auto species = [&](int s, auto firstc, auto lastc) {
+            constexpr bool FIRST = decltype(firstc)::value, LAST = decltype(lastc)::value;
+            const float* const in_n = in_s + sN;  // species s + 1
+            const float* const ina_n = ina_s + sNI;
+            const auto rout = mkrsrc(out_s, 4 * (int64_t)NB);
+            const auto rads = mkrsrc(outa_s, 4 * (int64_t)NIB);
+            const double pa = kc[KC * s], pd = kc[KC * s + 1];
+            double cq[4], w[3], nv[3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cq[q] = kc[KC * s + 2 + q];
+            for (int q = 0; q < 4; ++q) cq[q] = kc[KC * s + 2 + q];
 #pragma unroll
-        for (int g = 0; g < 3; ++g) {
-            nv[g] = kc[KC * s + 6 + g];
-            w[g] = act ? (double)av[g] + nv[g] : 0.0;
-        }
-        double red[NSUM];
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
-        auto field = [&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            const int f = 4 * s + q;
-            // field f has landed for the whole block once this wave has at most
-            // the operations issued after it outstanding: the loads of f+1, f+2
-            // and the stores of f-2, f-1 (2 (RLD + 1) + 2 * 2 with interface
-            // nodes in the wave, 2 RLD + 2 without); near the ends of the
-            // block's fields, wait for all
-            static_assert(RLD == 5, "wait counts assume 5 region loads per field");
-            if (f - fb < 2 || f + 2 >= fe) barrier_vm0();
-            else if (anyI) barrier_vm<16>();
-            else barrier_vm<12>();
-            if constexpr (q == 0) {
-                finish(pend2);
-                pend2 = -1;
+            for (int g = 0; g < 3; ++g) {
+                nv[g] = kc[KC * s + 6 + g];
+                w[g] = act ? (double)av[g] + nv[g] : 0.0;
             }
-            if constexpr (q == 1) {
-                fold();
-                pend2 = pend;
-                pend = -1;
-            }
-            // one live base index: addresses derived from it are not hoisted
-            // out of the loop (each would hold a register for the whole loop)
-            int c = cb;
-            asm volatile("" : "+v"(c));
-            const float* sb = stg.at<q>() + c;
-            // all 19 values first, then the arithmetic
-            float v[NL];
+            double red[NSUM];
 #pragma unroll
-            for (int k = 0; k < NL; ++k) v[k] = sb[region_at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
-            const double xc = (double)sb[region_at(1, 1, 1)];
-            double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
-            acc0 = __builtin_fma(cq[q], src, acc0);
+            for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
+            auto field = [&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const int f = 4 * s + q;
+                // field f has landed for the whole block once this wave has at
+                // most the operations issued after it outstanding: the loads of
+                // f+1, f+2 and the stores of f-2, f-1 (2 (RLD + 1) + 2 * 2 with
+                // interface nodes in the wave, 2 RLD + 2 without)
+                static_assert(RLD == 5, "wait counts assume 5 region loads per field");
+                if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
+                else if constexpr (ANYI) barrier_vm<16>();
+                else barrier_vm<12>();
+                if constexpr (q == 0) {
+                    finish(pend2);
+                    pend2 = -1;
+                }
+                if constexpr (q == 1) {
+                    fold();
+                    pend2 = pend;
+                    pend = -1;
+                }
+                // one live base offset: addresses derived from it are not
+                // hoisted out of the loop (each would hold a register for the
+                // whole loop)
+                int cbb = 4 * cb;
+                asm volatile("" : "+v"(cbb));
+                // volatile: one ds_read_b32 per value, its stencil offset in the
+                // instruction's immediate (merged pairs need a base register each)
+                using lvf = const volatile __attribute__((address_space(3))) float;
+                lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
+                // all 19 values first (the node's own first: the chain starts
+                // with it), then the arithmetic
+                const double xc = (double)sb[region_at(1, 1, 1)];
+                float v[NL];
 #pragma unroll
-            for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
-                if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
-                else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
-            }
-            double nvx = acc0 + acc1;
-            const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
-            if constexpr (q == 0) red[3] += act ? xc : 0.0;
-            else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
-            if (anyI) {  // wave-uniform: sorption (Eqs. 9, 10) where the wave has interface nodes
-                const double xa = (double)stg.at<q>()[RLD * BLK + tid];
-                const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
-                nvx = (nvx - fa) + fd;
-                bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), mkrsrc(outa_f, (int64_t)NI * 4), offa);
-                if constexpr (q == 0) red[4] += xa;
-                else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
-            }
-            bstore(sround(nvx, r), mkrsrc(out_f, (int64_t)N * 4), offn);
-            out_f += N;
-            outa_f += NI;
-            if (f + 3 < fe) issue(stg.at<(q + 3) & 3>());
+                for (int k = 0; k < NL; ++k) v[k] = sb[region_at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
+                acc0 = __builtin_fma(cq[q], src, acc0);
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
+                    if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
+                    else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
+                }
+                double nvx = acc0 + acc1;
+                const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
+                if constexpr (q == 0) red[3] += act ? xc : 0.0;
+                else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
+                if constexpr (ANYI) {  // sorption (Eqs. 9, 10) where the wave has interface nodes
+                    const double xa = (double)stg.at<q>()[RLD * BLK + tid];
+                    const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
+                    nvx = (nvx - fa) + fd;
+                    bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
+                    if constexpr (q == 0) red[4] += xa;
+                    else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
+                }
+                bstore(sround(nvx, r), rout, offn, q * NB);
+                // field f + 3: quantity 3 of this species, or quantity q - 1 of the next
+                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
+                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
+            };
+            field(std::integral_constant<int, 0>());
+            field(std::integral_constant<int, 1>());
+            field(std::integral_constant<int, 2>());
+            field(std::integral_constant<int, 3>());
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) rl[k * BLK + tid] = red[k];
+            pend = s;
+            in_s = in_n;
+            ina_s = ina_n;
+            out_s += sN;
+            outa_s += sNI;
         };
-        field(std::integral_constant<int, 0>());
-        field(std::integral_constant<int, 1>());
-        field(std::integral_constant<int, 2>());
-        field(std::integral_constant<int, 3>());
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) rl[k * BLK + tid] = red[k];
-        pend = s;
-    }
+        if (s1 - s0 == 1) {
+            species(s0, T_(), T_());
+        } else {
+            species(s0, T_(), F_());
+            for (int s = s0 + 1; s < s1 - 1; ++s) species(s, F_(), F_());
+            species(s1 - 1, F_(), T_());
+        }
+    };
+    if (anyI) run(T_());
+    else run(F_());
     barrier_vm0();
     finish(pend2);
     barrier_vm0();
@@ -1475,6 +1510,14 @@ lbmp_status upload(lbmp_mp* h) { return h->prec == LBMP_FP32 ? upload_geoms<floa
 
 // The z-march kernel addresses a group's fields and the link table through
 // one 32-bit buffer range each.
+// The LDS-DMA kernel addresses the 4 fields of a species through one buffer
+// resource: 16 bytes a node (interface node) must stay below the masking offset.
+bool dma_fits(const lbmp_mp* h) {
+    for (const auto& g : h->g)
+        if ((int64_t)16 * g.N >= (int64_t)OOB || (int64_t)16 * g.NI >= (int64_t)OOB) return false;
+    return true;
+}
+
 bool march_fits(const lbmp_mp* h, int G) {
     const int64_t es = h->prec == LBMP_FP32 ? 4 : 8;
     for (const auto& g : h->g) {
@@ -1502,7 +1545,7 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        const bool ok3 = v == 3 && K == 1 && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32;
+        const bool ok3 = v == 3 && K == 1 && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
         if (nread == 3 && (ok01 || ok2 || ok3)) {
             h->variant = v;
             h->K = K;
@@ -1538,7 +1581,7 @@ lbmp_status autotune(lbmp_mp* h) {
         for (int gs : {1, 2, 4})
             if ((gs <= maxS || gs == 1) && zs <= std::max(8, maxz) && march_fits(h, gs))
                 cand.push_back({zs, gs, 2});
-    if (h->prec == LBMP_FP32)
+    if (h->prec == LBMP_FP32 && dma_fits(h))
         for (int gs : {2, 4, 8, 16, 32, 64})
             if (gs <= maxS || gs == 2) cand.push_back({1, gs, 3});
     hipEvent_t e0, e1;
