@@ -700,8 +700,11 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 }
 
 // ------------------------------------------------------------------ variant 3
-// FP32 storage. For every field (species, quantity) of the block, the stencil
-// region — planes z-1, z and z+1 of a TX x TY tile with a one-node periodic
+// FP32 storage. A block owns a TX x (NH TY) tile of one z-plane, NH = 1 or 2
+// reduction tiles of TX x TY nodes (4 waves each, with their own partial
+// sums); a taller block re-reads fewer halo rows per node and synchronises
+// twice as many waves per barrier. For every field (species, quantity) of the block, the stencil
+// region — planes z-1, z and z+1 of the tile with a one-node periodic
 // halo — and the tile's adsorbed values are copied by the buffer unit straight
 // into LDS (buffer_load ... lds: lane i of a wave fills dword i of the wave's
 // destination; a lane out of range writes 0), three fields ahead of the field
@@ -711,14 +714,23 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // of a tile are adjacent, so the blocks that read a plane as centre and as
 // z-neighbour, and the blocks that share a tile's link data, are resident
 // together. Waves without an interface node skip the sorption arithmetic.
-constexpr int RX = TX + 2, RPL = RX * (TY + 2);  // one haloed plane
-constexpr int RREG = 3 * RPL;                    // planes z-1, z, z+1
+constexpr int RX = TX + 2;                       // haloed row
+template <int NH>
+struct DmaShape {
+    static constexpr int DTY = NH * TY, DBLK = NH * BLK;  // block tile rows, threads
+    static constexpr int RPL = RX * (DTY + 2);            // one haloed plane
+    static constexpr int RREG = 3 * RPL;                  // planes z-1, z, z+1
+    static constexpr int RLD = (RREG + DBLK - 1) / DBLK;  // region loads per thread and field
+    static constexpr int STAGE = (RLD + 1) * DBLK;        // dwords: region, then adsorbed values
+    // vector-memory operations a wave issues after a field's copy, up to the
+    // wait for it: the copies of the next two fields and the stores of the
+    // two before (with and without interface nodes in the wave)
+    static constexpr int WAIT_I = 2 * (RLD + 1) + 2 * 2, WAIT_N = 2 * RLD + 2;
+};
 // Region layout: row-interleaved planes, element (hy, pz, hx) at
 // (3 hy + pz) RX + hx, so the 19 stencil values of a node lie within 530
 // dwords of its (x-1, y-1, z-1) corner.
 __host__ __device__ constexpr int region_at(int hy, int pz, int hx) { return (3 * hy + pz) * RX + hx; }
-constexpr int RLD = (RREG + BLK - 1) / BLK;      // region loads per thread and field
-constexpr int STAGE = (RLD + 1) * BLK;           // dwords: region, then adsorbed values
 constexpr int DMA_GMAX = 64;                     // species per block
 constexpr int NSUM = 5;                          // per-node block sums of a species
 
@@ -774,28 +786,33 @@ struct Stages {
     __device__ __forceinline__ float* at() const { return p[Q]; }
 };
 
-__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
+template <int NH>
+__global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
                                                int64_t nblocks, const Ctl* __restrict__ ctl) {
+    using SH = DmaShape<NH>;
+    constexpr int DTY = SH::DTY, DBLK = SH::DBLK, RREG = SH::RREG, RLD = SH::RLD, STAGE = SH::STAGE;
     __shared__ __align__(16) float st0[STAGE];
     __shared__ __align__(16) float st1[STAGE];
     __shared__ __align__(16) float st2[STAGE];
     __shared__ __align__(16) float st3[STAGE];
-    __shared__ __align__(16) double rl[NSUM * BLK];  // per-node sums of a species
-    __shared__ __align__(16) double l2[NRED * 64];   // partial sums of 4 nodes, by series slot
+    __shared__ __align__(16) double rl[NSUM * DBLK];  // per-node sums of a species
+    __shared__ __align__(16) double l2[NH * NRED * 64]; // per half: partial sums of 4 nodes, by series slot
     float* const tag = nullptr;
     const int64_t lb = xcd_remap(blockIdx.x, nblocks);
     const int gi = find_geom(geoms, ngeom, lb);
     const GeomDev<float>& G = geoms[gi];
     const int64_t local = lb - G.blk0;
     const int grp = (int)(local % G.ngrp);
-    const int64_t tile = local / G.ngrp;
+    const int64_t btile = local / G.ngrp;  // block tile; reduction tiles NH btile + half
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int ntx = (nx + TX - 1) / TX;
-    const int z = (int)(tile % nz);
-    const int64_t cxy = tile / nz;
-    const int x0 = (int)(cxy % ntx) * TX, y0 = (int)(cxy / ntx) * TY;
+    const int z = (int)(btile % nz);
+    const int64_t cxy = btile / nz;
+    const int x0 = (int)(cxy % ntx) * TX, y0 = (int)(cxy / ntx) * DTY;
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int hf = wv >> 2, w4 = wv & 3;        // half of the block, wave within it
+    const int64_t tile = NH * btile + hf;       // this wave's reduction tile
     const int x = x0 + lx, y = y0 + ly;
     const bool inplane = x < nx && y < ny;
     const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
@@ -804,23 +821,23 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
     const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
     const int64_t ntile = G.ntile;
     double* const part = G.part;
-    if (!__syncthreads_or(act)) {  // a tile without fluid: zero sums
-        for (int i = tid; i < NRED * (s1 - s0); i += BLK)
-            part[((int64_t)(s0 + i / NRED) * ntile + tile) * NRED + i % NRED] = 0.0;
+    if (!__syncthreads_or(act)) {  // a tile without fluid: zero sums of every half
+        for (int i = tid; i < NH * NRED * (s1 - s0); i += DBLK)
+            part[((int64_t)(s0 + i / (NH * NRED)) * ntile + NH * btile + (i / NRED) % NH) * NRED + i % NRED] = 0.0;
         return;
     }
     const int sl = act ? G.slot[n] : -1;
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
     const int offn = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
-    // this thread's share of the stencil region, element e = j * BLK + tid
+    // this thread's share of the stencil region, element e = j * DBLK + tid
     int voff[RLD];
     // (solid nodes hold zero fields and are never written: their elements are
     // masked like the padding, so the copy fetches fluid nodes only and the
     // out-of-range lanes write the same zeros)
 #pragma unroll
     for (int j = 0; j < RLD; ++j) {
-        const int e = j * BLK + tid;
+        const int e = j * DBLK + tid;
         const int hy = e / (3 * RX), pz = (e / RX) % 3, hx = e % RX;
         const int m = e < RREG ? modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
         voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
@@ -857,9 +874,9 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
         float* dst = stg.at<qp>() + wv * 64;
 #pragma unroll
         for (int j = 0; j < RLD; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * BLK), 4, voff[j], qp * NB, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * DBLK), 4, voff[j], qp * NB, 0, 0);
         if constexpr (decltype(anyc)::value)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(iab, 4 * (int64_t)NIB), LBMP_LDS(dst + RLD * BLK), 4,
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(iab, 4 * (int64_t)NIB), LBMP_LDS(dst + RLD * DBLK), 4,
                                                      offa, qp * NIB, 0, 0);
     };
     // Block sums of a species in a fixed order, one step per field barrier.
@@ -881,20 +898,21 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
         // pair (partial of sum w over nodes 4 ln..4 ln+3, partial of sum 4 over
         // nodes 64 w + 4 (ln % 16) ..+3), one store: a second LDS store in a
         // row makes the compiler wait for all DMA in flight
-        const double* p = rl + wv * BLK + ln * 4;
-        const double* p4 = rl + 4 * BLK + wv * 64 + (ln & 15) * 4;
+        const double* p = rl + w4 * DBLK + hf * BLK + ln * 4;
+        const double* p4 = rl + 4 * DBLK + wv * 64 + (ln & 15) * 4;  // wv * 64 = hf * BLK + w4 * 64
         using d2 = double __attribute__((ext_vector_type(2)));
         d2 v;
         v.x = ((p[0] + p[1]) + p[2]) + p[3];
         v.y = ((p4[0] + p4[1]) + p4[2]) + p4[3];
-        *reinterpret_cast<d2*>(l2 + 2 * (wv * 64 + ln)) = v;
+        *reinterpret_cast<d2*>(l2 + hf * (NRED * 64) + 2 * (w4 * 64 + ln)) = v;
     };
     auto finish = [&](int s) {
-        const int k = 2 * wv + (ln >> 5), j = ln & 31;
+        const int k = 2 * w4 + (ln >> 5), j = ln & 31;
         // slots 0-3: partials 2j, 2j+1 of sum k; slot 7: partials 2j, 2j+1
         // of sum 4 (partial i from wave i / 16, lane i % 16)
         const int i0 = k < 4 ? 2 * (k * 64 + 2 * j) : 2 * ((j >> 3) * 64 + ((2 * j) & 15)) + 1;
-        double v = l2[i0] + l2[i0 + 2];
+        const double* l2h = l2 + hf * (NRED * 64);
+        double v = l2h[i0] + l2h[i0 + 2];
         v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
         v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
         v += dpp_f64<0x124>(v);   // row_ror:4
@@ -949,10 +967,9 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                 // most the operations issued after it outstanding: the loads of
                 // f+1, f+2 and the stores of f-2, f-1 (2 (RLD + 1) + 2 * 2 with
                 // interface nodes in the wave, 2 RLD + 2 without)
-                static_assert(RLD == 5, "wait counts assume 5 region loads per field");
                 if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
-                else if constexpr (ANYI) barrier_vm<16>();
-                else barrier_vm<12>();
+                else if constexpr (ANYI) barrier_vm<SH::WAIT_I>();
+                else barrier_vm<SH::WAIT_N>();
                 if constexpr (q == 0) {
                     finish(pend2);
                     pend2 = -1;
@@ -989,7 +1006,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
                 if constexpr (q == 0) red[3] += act ? xc : 0.0;
                 else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
                 if constexpr (ANYI) {  // sorption (Eqs. 9, 10) where the wave has interface nodes
-                    const double xa = (double)stg.at<q>()[RLD * BLK + tid];
+                    const double xa = (double)stg.at<q>()[RLD * DBLK + tid];
                     const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
                     nvx = (nvx - fa) + fd;
                     bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
@@ -1006,7 +1023,7 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) k
             field(std::integral_constant<int, 2>());
             field(std::integral_constant<int, 3>());
 #pragma unroll
-            for (int k = 0; k < NSUM; ++k) rl[k * BLK + tid] = red[k];
+            for (int k = 0; k < NSUM; ++k) rl[k * DBLK + tid] = red[k];
             pend = s;
             in_s = in_n;
             ina_s = ina_n;
@@ -1323,6 +1340,8 @@ constexpr int GRAPH_CHUNK = 64;
 
 int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
+    // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
+    if (variant == 3) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + K * TY - 1) / (K * TY)) * f->nz;
     if (variant >= 1) return (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * zb;
     return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
@@ -1418,7 +1437,8 @@ lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species,
         g.N = g.flow->N;
         g.NI = g.flow->ni;
         g.nf = g.flow->nf;
-        g.ntile_max = std::max(ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1));
+        g.ntile_max = std::max({ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1), ntile_for(g.flow, 1, 3),
+                                ntile_for(g.flow, 2, 3)});
     }
     return h;
 }
@@ -1428,8 +1448,10 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     dim3 grid((unsigned)h->nblocks);
     if (h->variant == 3) {
-        if constexpr (std::is_same<T, float>::value)
-            k_mp_dma<<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+        if constexpr (std::is_same<T, float>::value) {
+            if (h->K == 2) k_mp_dma<2><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else k_mp_dma<1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+        }
         return;
     }
     if (h->variant == 2) {
@@ -1489,7 +1511,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
         d.ntile = ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += d.ntile * d.ngrp;
+        blk += (h->variant == 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variant 3: one block per K tiles
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -1545,7 +1567,7 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        const bool ok3 = v == 3 && K == 1 && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
+        const bool ok3 = v == 3 && (K == 1 || K == 2) && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
         if (nread == 3 && (ok01 || ok2 || ok3)) {
             h->variant = v;
             h->K = K;
@@ -1554,7 +1576,7 @@ lbmp_status autotune(lbmp_mp* h) {
         }
         return fail(LBMP_EINVAL, "LBMP_TILE must be 'variant,K,species_per_block': variant 0|1 with K 1|2, "
                                  "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
-                                 "(FP32 only) with K 1 and at most 64 species per block");
+                                 "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles) and at most 64 species per block");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1583,7 +1605,8 @@ lbmp_status autotune(lbmp_mp* h) {
                 cand.push_back({zs, gs, 2});
     if (h->prec == LBMP_FP32 && dma_fits(h))
         for (int gs : {2, 4, 8, 16, 32, 64})
-            if (gs <= maxS || gs == 2) cand.push_back({1, gs, 3});
+            for (int K : {1, 2})
+                if (gs <= maxS || gs == 2) cand.push_back({K, gs, 3});
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
     LBMP_HIP(hipEventCreate(&e1));
