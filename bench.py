@@ -80,16 +80,17 @@ def build_porous(lb, inputs):
     return [fl], [{"D_b": D_B, "k_a": ka, "k_d": kd}], [f], [n]
 
 
-def traffic_record():
+def traffic_record(tile: str):
     """Measured HBM bytes per launch of the propagation kernel, if taken on the
-    current kernel source (profiles/mp_step_traffic.json)."""
+    current kernel source with the same tile choice ("variant,K,species per
+    block") as this run (profiles/mp_step_traffic.json)."""
     path = os.path.join(ROOT, "profiles", "mp_step_traffic.json")
     src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha:
+    if rec.get("kernel_source_sha256") != sha or rec.get("tile") != tile:
         return None
     return rec.get("bytes_per_launch")
 
@@ -142,6 +143,7 @@ def traffic_from_counters(root: str, copy_bytes: int) -> dict:
     w_scale = copy_bytes / (max(cw) * 1024.0)
     src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
     return {"kernel": "k_mp_dma", "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+            "tile": os.environ.get("LBMP_TILE"),
             "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
             "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
             "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale}
@@ -247,7 +249,7 @@ def main():
     alg = sum(n_species * (32 * f + 32 * n) + 16 * f for f, n in zip(nf, ni))
     k_avg_s = k_ms / 1e3 / args.steps
     achieved = alg / k_avg_s / 1e9
-    traffic = traffic_record()
+    traffic = traffic_record(f'{st["kernel_variant"]},{st["tile_k"]},{st["species_per_block"]}')
     # accuracy and invariants of this run
     out = lbmp.mp_vacf(mp, len(flows) - 1, total, 1)
     mass_err = float(np.abs(out["mass"].sum(axis=1) - 1).max())
