@@ -170,6 +170,34 @@ def cpu_baseline(inputs, steps: int):
                       f"FP64 stay form incl. its per-run set-up; {el:.1f}s"}
 
 
+def sequential_compare(lb, flows, species, steps: int, warmup: int) -> dict:
+    """The batched run against one run per (geometry, species) pair, each a
+    handle of its own advancing the same number of steps through mp_step_n
+    (graph replay), wall clock around the queued steps."""
+    def timed(mp):
+        lb.mp_step_n(mp, warmup)
+        mp.stream.synchronize()
+        t0 = time.perf_counter()
+        lb.mp_step_n(mp, steps)
+        mp.stream.synchronize()
+        return time.perf_counter() - t0
+
+    mp = lb.mp_init(flows, species, lb.LBMP_FP32, warmup + steps)
+    tb = timed(mp)
+    mp.free()
+    ts, runs = 0.0, 0
+    for fl, sp in zip(flows, species):
+        for s in range(len(sp["k_a"])):
+            one = {"D_b": sp["D_b"], "k_a": sp["k_a"][s:s + 1], "k_d": sp["k_d"][s:s + 1]}
+            mp = lb.mp_init(fl, one, lb.LBMP_FP32, warmup + steps)
+            ts += timed(mp)
+            mp.free()
+            runs += 1
+    return {"metric": "batched vs sequential moment propagation", "steps": steps, "warmup": warmup,
+            "batched_ms_per_step": tb / steps * 1e3, "sequential_runs": runs,
+            "sequential_ms_per_step": ts / steps * 1e3, "speedup": ts / tb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +208,8 @@ def main():
     ap.add_argument("--workload", choices=("slits", "porous256"), default="slits",
                     help="slits: the batched-slit configuration (default); porous256: the 256^3 sphere "
                          "pack with 16 species (no CPU baseline)")
+    ap.add_argument("--sequential", action="store_true",
+                    help="only compare the batched slit run with one run per (geometry, species) pair")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (known traffic, to scale HBM counters)")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="only summarise rocprofv3 CSV output under DIR")
@@ -216,6 +246,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "launches": 5}))
         return
     lbmp.load_library()
+    if args.sequential:
+        flows, species, nf, ni = build_workload(lbmp, inputs)
+        print(json.dumps(sequential_compare(lbmp, flows, species, args.steps, args.warmup)), flush=True)
+        return
     if args.workload == "slits":
         flows, species, nf, ni = build_workload(lbmp, inputs)
         n_species = N_SPECIES
