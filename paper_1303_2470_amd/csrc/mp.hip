@@ -851,6 +851,11 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     float av[3];
 #pragma unroll
     for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offn);
+    // per-node VACF weights without a branch on the node's class
+    const double actd = act ? 1.0 : 0.0;
+    double avd[3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) avd[g] = act ? (double)av[g] : 0.0;
     const int64_t t = ctl->t;
     const uint32_t rbase = hash32((uint32_t)n * 0x9e3779b9u ^ hash32((uint32_t)t ^ ((uint32_t)gi << 24)));
     const float* const Xin = (t & 1) ? G.X1 : G.X0;
@@ -868,16 +873,37 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     // 16 N_I below OOB for this kernel).
     const int NB = N * 4, NIB = NI * 4;
     const int64_t sN = 4 * (int64_t)N, sNI = 4 * (int64_t)NI;
+    // The immediate offset of an LDS-DMA load moves both the memory address and
+    // the LDS destination, so copies whose destinations lie within 4 KB share
+    // one LDS base (M0): copy j (and the adsorbed values, as copy RLD) goes to
+    // base j / GJ at immediate (j % GJ) * DBLK * 4, taken back from its memory
+    // offset; the resources start 4 KB below the species so that offset stays
+    // non-negative.
+    constexpr int GJ = 4096 / (DBLK * 4);  // copies per LDS base
+    int vo[RLD];
+#pragma unroll
+    for (int j = 0; j < RLD; ++j) vo[j] = voff[j] == OOB ? OOB : voff[j] + 4096 - (j % GJ) * DBLK * 4;
+    const int voa = offa == OOB ? OOB : offa + 4096 - (RLD % GJ) * DBLK * 4;
+    static_assert(RLD <= 5, "copies are unrolled for at most 5 region loads");
     auto issue = [&](auto qpc, auto anyc, const float* ib, const float* iab) {
         constexpr int qp = decltype(qpc)::value;  // quantity (and stage) of the copied field
-        const auto rin = mkrsrc(ib, 4 * (int64_t)NB);
+        const auto rin = mkrsrc(reinterpret_cast<const char*>(ib) - 4096, 4 * (int64_t)NB + 4096);
         float* dst = stg.at<qp>() + wv * 64;
-#pragma unroll
-        for (int j = 0; j < RLD; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + j * DBLK), 4, voff[j], qp * NB, 0, 0);
+        auto copy = [&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr (j < RLD)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + (j / GJ) * GJ * DBLK), 4, vo[j],
+                                                         qp * NB, (j % GJ) * DBLK * 4, 0);
+        };
+        copy(std::integral_constant<int, 0>());
+        copy(std::integral_constant<int, 1>());
+        copy(std::integral_constant<int, 2>());
+        copy(std::integral_constant<int, 3>());
+        copy(std::integral_constant<int, 4>());
         if constexpr (decltype(anyc)::value)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(mkrsrc(iab, 4 * (int64_t)NIB), LBMP_LDS(dst + RLD * DBLK), 4,
-                                                     offa, qp * NIB, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096),
+                LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa, qp * NIB, (RLD % GJ) * DBLK * 4, 0);
     };
     // Block sums of a species in a fixed order, one step per field barrier.
     // Per node: the drift-corrected VACF terms X_g (a_g - V_g) - V_g X_ads,g
@@ -955,7 +981,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
             for (int g = 0; g < 3; ++g) {
                 nv[g] = kc[KC * s + 6 + g];
-                w[g] = act ? (double)av[g] + nv[g] : 0.0;
+                w[g] = __builtin_fma(actd, nv[g], avd[g]);  // av + nv, 0 off the fluid
             }
             double red[NSUM];
 #pragma unroll
@@ -1532,11 +1558,12 @@ lbmp_status upload(lbmp_mp* h) { return h->prec == LBMP_FP32 ? upload_geoms<floa
 
 // The z-march kernel addresses a group's fields and the link table through
 // one 32-bit buffer range each.
-// The LDS-DMA kernel addresses the 4 fields of a species through one buffer
-// resource: 16 bytes a node (interface node) must stay below the masking offset.
+// The LDS-DMA kernel addresses the 4 fields of a species (and 4 KB below them)
+// through one buffer resource: 16 bytes a node (interface node) plus 4 KB must
+// stay below the masking offset.
 bool dma_fits(const lbmp_mp* h) {
     for (const auto& g : h->g)
-        if ((int64_t)16 * g.N >= (int64_t)OOB || (int64_t)16 * g.NI >= (int64_t)OOB) return false;
+        if ((int64_t)16 * g.N + 4096 >= (int64_t)OOB || (int64_t)16 * g.NI + 4096 >= (int64_t)OOB) return false;
     return true;
 }
 
