@@ -57,27 +57,14 @@ def build_workload(lb, inputs):
     return flows, species, nf, ni
 
 
-POROUS_N, POROUS_R, POROUS_PHI, POROUS_SPECIES, POROUS_SEED = 256, 8, 0.4, 16, 2024
-
-
-def build_porous(lb, inputs):
-    """256^3 periodic Boolean sphere pack (R = 8, porosity 0.4), BGK flow solved
-    at a reference force and rescaled to Pe = 10 on the sample length (Stokes
-    regime), 16 species with (k_a, k_d) log-uniform in [1e-4, 1e-1]."""
-    t0 = time.time()
-    mask = inputs.sphere_pack(POROUS_N, POROUS_R, POROUS_PHI, seed=POROUS_SEED)
-    log(f"sphere pack {POROUS_N}^3: {time.time() - t0:.1f}s")
-    t0 = time.time()
-    ref = lb.lb_flow_solve(mask, 1.0, [1e-6, 0.0, 0.0], 1e-6, 200000)
-    u = ref.velocity()
-    ref.free()
-    vbar = float(u[0][mask == 0].mean())
-    u *= (PECLET * D_B / POROUS_N) / vbar
-    fl = lb.lb_flow_from_velocity(mask, u)
-    log(f"flow: {time.time() - t0:.1f}s")
-    ka, kd = inputs.loguniform_rates(POROUS_SPECIES, 1e-4, 1e-1, seed=POROUS_SEED + 2)
+def build_porous(lb):
+    """The 256^3 periodic Boolean sphere pack (R = 8, porosity 0.4) with BGK
+    flow rescaled to Pe = 10 on the sample length, 16 species with (k_a, k_d)
+    log-uniform in [1e-4, 1e-1] (paper_1303_2470_amd.porous)."""
+    from paper_1303_2470_amd import porous
+    fl, sp = porous.build(lb, log=log)
     _, f, n = fl.classes()
-    return [fl], [{"D_b": D_B, "k_a": ka, "k_d": kd}], [f], [n]
+    return [fl], [sp], [f], [n]
 
 
 def traffic_record(tile: str):
@@ -257,9 +244,10 @@ def main():
         workload = ("batched slits W=16,32,48,64 fluid layers x 64x64 lateral, 64 species each (k_a,k_d "
                     "log-uniform 1e-4..1e-1), D_b=1e-2, Poiseuille Pe=10, FP32 propagation + FP64 sums")
     else:
-        flows, species, nf, ni = build_porous(lbmp, inputs)
-        n_species = POROUS_SPECIES
-        lat_nodes = POROUS_N ** 3
+        flows, species, nf, ni = build_porous(lbmp)
+        from paper_1303_2470_amd import porous
+        n_species = porous.N_SPECIES
+        lat_nodes = porous.N ** 3
         workload = ("256^3 periodic Boolean sphere pack R=8 porosity 0.4, 16 species (k_a,k_d log-uniform "
                     "1e-4..1e-1), D_b=1e-2, BGK flow at Pe=10, FP32 propagation + FP64 sums")
         args.no_cpu_baseline = True

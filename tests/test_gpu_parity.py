@@ -152,7 +152,7 @@ def test_state_matches_oracle_fields(lb):
     mp.free()
 
 
-@pytest.mark.parametrize("pe", [10.0, 100.0])
+@pytest.mark.parametrize("pe", [1.0, 10.0, 100.0])
 def test_poiseuille_c2_full_length_fp32(lb, pe):
     """64x64x66 slit, BGK flow at Pe, 1e5 FP32 steps, k_a = 5e-3, k_d = 2e-3,
     against the oracle's laterally reduced column (flow and propagation)."""

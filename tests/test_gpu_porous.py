@@ -83,3 +83,20 @@ def test_sphere_pack_256_full_size_samples(lb):
     for i, s in enumerate((0, 15)):
         assert np.allclose(out["mass"][i], refs[s]["mass"][:, -1], rtol=1e-5, atol=1e-9)
     mp.free()
+
+
+def test_porous_module_log_grid_small(lb):
+    """The porous-medium workload module on a small medium (24^3, R = 3):
+    log-grid samples equal the full series, conservation, and the oracle at
+    the first steps for two species."""
+    from paper_1303_2470_amd import porous
+    r = porous.run(lb, 300, 10, n=24, radius=3, n_species=4, seed=77)
+    assert r["D"].shape == (4, 3, len(r["t"])) and r["t"][-1] == 300
+    assert np.abs(r["mass"].sum(axis=1) - 1).max() < 1e-5
+    mask = inputs.sphere_pack(24, 3, porous.POROSITY, seed=77)
+    u = r["flow"].velocity()
+    for s in (0, 3):
+        ref = oracle.vacf(mask, u, 12 * porous.D_B, r["k_a"][s], r["k_d"][s], 2)
+        Dref = oracle.d_of_t(ref["Z"], ref["V"]) / porous.D_B
+        assert np.abs(r["D"][s][:, :3] - Dref).max() <= 1e-5 * np.abs(Dref).max(), s
+    r["flow"].free()

@@ -37,3 +37,11 @@ def test_refine_stays_in_bounds():
 def test_log_times():
     t = inverse.log_times(3000)
     assert t[0] == 1 and t[-1] == 3000 and np.all(np.diff(t) > 0)
+
+
+def test_porous_log_grid():
+    from paper_1303_2470_amd import porous
+    g = porous.log_grid(20000, 10)
+    assert g[0] == 0 and g[1] == 1 and g[-1] == 20000 and np.all(np.diff(g) > 0)
+    # about 10 points per decade once the integers thin out
+    assert 9 <= np.sum((g >= 1000) & (g < 10000)) <= 11
