@@ -700,15 +700,16 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 }
 
 // ------------------------------------------------------------------ variant 3
-// FP32 storage. A block owns a TX x (NH TY) tile of one z-plane, NH = 1 or 2
+// FP32 storage. A block owns a TX x (NH TY) tile of one z-plane: NH = 1 or 2
 // reduction tiles of TX x TY nodes (4 waves each, with their own partial
 // sums); a taller block re-reads fewer halo rows per node and synchronises
-// twice as many waves per barrier. For every field (species, quantity) of the block, the stencil
-// region — planes z-1, z and z+1 of the tile with a one-node periodic
-// halo — and the tile's adsorbed values are copied by the buffer unit straight
-// into LDS (buffer_load ... lds: lane i of a wave fills dword i of the wave's
-// destination; a lane out of range writes 0), three fields ahead of the field
-// being updated, through four LDS stages (stage = quantity q). Nothing passes
+// twice as many waves per barrier. For every field (species, quantity) of the
+// block, the stencil region — planes z-1, z and z+1 of the tile with a
+// one-node periodic halo — and the tile's adsorbed values are copied by the
+// buffer unit straight into LDS (buffer_load ... lds: lane i of a wave fills
+// dword i of the wave's destination; a lane out of range writes 0), three
+// fields ahead of the field being updated, through four LDS stages (stage =
+// quantity q). Nothing passes
 // through registers on its way in, so the tile's link data stay in registers
 // for all the fields of the block. Tiles run z-fastest and the species groups
 // of a tile are adjacent, so the blocks that read a plane as centre and as
@@ -773,10 +774,6 @@ __device__ __forceinline__ double dpp_bcast15(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x142, 0xA, 0xF, false);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
-
-// Read-only tables in the constant address space: uniform loads from it are
-// scalar loads, which do not queue behind the vector-memory traffic.
-using cfloat = const __attribute__((address_space(4))) float;
 
 // Four LDS stages as separate objects, so that the compiler's own tracking of
 // LDS DMA can tell a stage being read from the stages still being filled.
@@ -867,10 +864,10 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const Stages stg{{st0, st1, st2, st3}};
 
     // Buffer resources span the 4 fields of one species; the field of quantity
-    // q sits at soffset q * (bytes per field). A masked offset (OOB) lies
-    // beyond the 4 fields whether or not the hardware adds soffset before the
-    // range check, and OOB + 3 fields does not wrap (the host keeps 16 N and
-    // 16 N_I below OOB for this kernel).
+    // q sits at soffset q * (bytes per field). The range check applies to
+    // voffset + soffset + immediate: a masked offset (OOB) stays beyond the
+    // range and OOB + 3 fields + 4 KB does not wrap (the host keeps 16 N + 4 KB
+    // and 16 N_I + 4 KB below OOB for this kernel).
     const int NB = N * 4, NIB = NI * 4;
     const int64_t sN = 4 * (int64_t)N, sNI = 4 * (int64_t)NI;
     // The immediate offset of an LDS-DMA load moves both the memory address and
