@@ -185,6 +185,43 @@ def sequential_compare(lb, flows, species, steps: int, warmup: int) -> dict:
             "sequential_ms_per_step": ts / steps * 1e3, "speedup": ts / tb}
 
 
+def surrogate_throughput(lb, n: int, batch_max: int, train_batch: int, reps: int) -> dict:
+    """Inference and training-step throughput of the BF16-MFMA network on
+    random inputs (weights from its own initialisation): samples/s and the
+    GEMM work per second against the dense BF16 MFMA peak."""
+    import torch
+    # flop per sample: 2 x (multiply-adds of 6->256, 256->256, 256->256, 256->1)
+    fwd = 2 * (6 * 256 + 256 * 256 + 256 * 256 + 256)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.rand((n, 6), device="cuda", generator=g, dtype=torch.float32)
+    sg = lb.Surrogate(batch_max, seed=1)
+    out = sg.predict(x)
+    sg.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sg.predict(x, out)
+    sg.sync()
+    tp = (time.perf_counter() - t0) / reps
+    sg.free()
+    st = lb.Surrogate(train_batch, seed=1)
+    y = torch.rand((train_batch,), device="cuda", generator=g, dtype=torch.float32)
+    xt = x[:train_batch].contiguous()
+    st.train_step(xt, y, None, train_batch, 1e-4)
+    st.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps * 10):
+        st.train_step(xt, y, None, train_batch, 1e-4)
+    st.sync()
+    tt = (time.perf_counter() - t0) / (reps * 10)
+    st.free()
+    peak = 2.5e15
+    return {"metric": "surrogate throughput", "predict_rows": n, "predict_chunk": batch_max,
+            "predict_s": tp, "predict_samples_per_s": n / tp, "predict_tflops": fwd * n / tp / 1e12,
+            "predict_frac_bf16_peak": fwd * n / tp / peak,
+            "train_batch": train_batch, "train_step_s": tt, "train_samples_per_s": train_batch / tt,
+            "train_tflops": 3 * fwd * train_batch / tt / 1e12, "peak_tflops_bf16": peak / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +232,8 @@ def main():
     ap.add_argument("--workload", choices=("slits", "porous256"), default="slits",
                     help="slits: the batched-slit configuration (default); porous256: the 256^3 sphere "
                          "pack with 16 species (no CPU baseline)")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="only time the surrogate network: inference on 2^20 rows, training steps")
     ap.add_argument("--sequential", action="store_true",
                     help="only compare the batched slit run with one run per (geometry, species) pair")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -233,6 +272,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "launches": 5}))
         return
     lbmp.load_library()
+    if args.surrogate:
+        print(json.dumps(surrogate_throughput(lbmp, 1 << 20, 1 << 16, 1024, 20)), flush=True)
+        return
     if args.sequential:
         flows, species, nf, ni = build_workload(lbmp, inputs)
         print(json.dumps(sequential_compare(lbmp, flows, species, args.steps, args.warmup)), flush=True)

@@ -7,9 +7,13 @@
 //   forward   Z_l = A_{l-1} W_l^T + b_l,  A_l = silu(Z_l)      (M = batch, N = out, K = in)
 //   backward  dA_{l-1} = dZ_l W_l,  dZ_{l-1} = dA_{l-1} * silu'(Z_{l-1})   (N = in, K = out)
 //             dW_l = dZ_l^T A_{l-1}                            (M = out, N = in, K = batch)
-// A wave computes one 32x32 output tile; operands are read straight from
-// global memory (the matrices are at most 256 wide: latency, not bandwidth,
-// bounds these GEMMs).
+// Large GEMMs (M, N multiples of 128, K of 32) run k_gemm_lds: a block of 4
+// waves owns a 128 x 128 output tile, stages 32-wide K slices of both operands
+// through LDS (transposing operands stored K-major on the way) and each wave
+// accumulates a 64 x 64 sub-tile as 2 x 2 MFMA tiles, so every operand read
+// from LDS feeds two MFMAs. The small ones (the padded 32-wide input and
+// output layers) run k_gemm: a wave computes one 32x32 output tile with
+// operands read straight from global memory.
 #include <cmath>
 #include <vector>
 
@@ -38,6 +42,33 @@ __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z));
 __device__ __forceinline__ float silu_grad(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
+}
+
+// Epilogue of one 32x32 MFMA tile at (m0, n0) of C (see k_gemm).
+template <int epi>
+__device__ __forceinline__ void epilogue(const f32x16& acc, int m0, int n0, int lane, int N,
+                                         const float* __restrict__ bias, const float* __restrict__ aux,
+                                         float* __restrict__ out0, __bf16* __restrict__ out1) {
+    // accumulator layout: element v of lane l is C[row][col] with col = l % 32,
+    // row = 8*(v/4) + 4*(l/32) + v%4
+    const int col = n0 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const size_t o = (size_t)row * N + col;
+        float c = acc[v];
+        if (epi == EPI_HIDDEN) {
+            c += bias[col];
+            out0[o] = c;
+            out1[o] = (__bf16)silu(c);
+        } else if (epi == EPI_OUT) {
+            out0[o] = c + bias[col];
+        } else if (epi == EPI_DACT) {
+            out1[o] = (__bf16)(c * silu_grad(aux[o]));
+        } else {
+            out0[o] = c;
+        }
+    }
 }
 
 // C[M][N] = sum_k A(m, k) B(k, n), bf16 operands, fp32 accumulation.
@@ -76,25 +107,159 @@ __global__ void __launch_bounds__(256) k_gemm(const __bf16* __restrict__ A, int 
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
-    // accumulator layout: element v of lane l is C[row][col] with col = l % 32,
-    // row = 8*(v/4) + 4*(l/32) + v%4
-    const int col = n0 + r;
+    epilogue<epi>(acc, m0, n0, lane, N, bias, aux, out0, out1);
+}
+
+constexpr int TBM = 128, TBN = 128, TBK = 32, TPITCH = TBK + 8;  // LDS rows padded against bank conflicts
+
+// Same operation and epilogues as k_gemm, for M, N multiples of 128 and K of
+// 32; one block (256 threads) per 128 x 128 output tile.
+template <bool a_km, bool b_nk, int epi>
+__global__ void __launch_bounds__(256) k_gemm_lds(const __bf16* __restrict__ A, int lda,
+                                                  const __bf16* __restrict__ B, int ldb, int M, int N, int K,
+                                                  const float* __restrict__ bias, const float* __restrict__ aux,
+                                                  float* __restrict__ out0, __bf16* __restrict__ out1) {
+    __shared__ __align__(16) __bf16 As[TBM * TPITCH];  // [m][k]
+    __shared__ __align__(16) __bf16 Bs[TBN * TPITCH];  // [n][k]
+    const int tiles_n = N / TBN;
+    const int m0 = (blockIdx.x / tiles_n) * TBM, n0 = (blockIdx.x % tiles_n) * TBN;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    f32x16 acc[2][2] = {};
+    // one 8-element chunk of a K-contiguous operand (rows x 32) or of a
+    // K-major one (32 x cols) per thread and i
+    auto stage = [&](const __bf16* X, int ldx, int x0, int k0, bool x_k_contiguous, __bf16* S) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int row = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const size_t o = (size_t)row * N + col;
-        float c = acc[v];
-        if (epi == EPI_HIDDEN) {
-            c += bias[col];
-            out0[o] = c;
-            out1[o] = (__bf16)silu(c);
-        } else if (epi == EPI_OUT) {
-            out0[o] = c + bias[col];
-        } else if (epi == EPI_DACT) {
-            out1[o] = (__bf16)(c * silu_grad(aux[o]));
-        } else {
-            out0[o] = c;
+        for (int i = 0; i < 2; ++i) {
+            const int c = t + 256 * i;
+            if (x_k_contiguous) {
+                const int row = c >> 2, kc = (c & 3) * 8;
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(X + (size_t)(x0 + row) * ldx + k0 + kc);
+                *reinterpret_cast<bf16x8*>(S + row * TPITCH + kc) = v;
+            } else {
+                const int kk = c >> 4, xc = (c & 15) * 8;
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(X + (size_t)(k0 + kk) * ldx + x0 + xc);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) S[(xc + j) * TPITCH + kk] = v[j];
+            }
         }
+    };
+    for (int k0 = 0; k0 < K; k0 += TBK) {
+        stage(A, lda, m0, k0, a_km, As);
+        stage(B, ldb, n0, k0, b_nk, Bs);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TBK; kk += 16) {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x8*>(As + (wm + 32 * i + r) * TPITCH + kk + kh);
+                b[i] = *reinterpret_cast<const bf16x8*>(Bs + (wn + 32 * i + r) * TPITCH + kk + kh);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            epilogue<epi>(acc[i][j], m0 + wm + 32 * i, n0 + wn + 32 * j, lane, N, bias, aux, out0, out1);
+}
+
+// Fused inference: one block (4 waves) per FS samples runs all four layers
+// with the activations in LDS (two buffers, layer l reads one and writes the
+// other) and the weights read as MFMA operands straight from global memory,
+// where all blocks share them in L2. The arithmetic is that of the layer
+// GEMMs (bf16 operands, fp32 accumulation in increasing K, bias and SiLU in
+// fp32, activations rounded to bf16), so predictions equal the unfused path's.
+constexpr int FS = 64;               // samples per block
+constexpr int APITCH = WIDTH + 8;    // bf16 per activation row (padded against bank conflicts)
+
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ x, int64_t n,
+                                                     const float* __restrict__ norm,
+                                                     const __bf16* __restrict__ W0, const float* __restrict__ b0,
+                                                     const __bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                     const __bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                     const __bf16* __restrict__ W3, const float* __restrict__ b3,
+                                                     float* __restrict__ y) {
+    __shared__ __align__(16) __bf16 act[2][FS * APITCH];
+    const int64_t s0 = (int64_t)blockIdx.x * FS;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    // normalised features, zero padded to PAD_IN columns
+    for (int i = t; i < FS * PAD_IN; i += 256) {
+        const int row = i / PAD_IN, c = i % PAD_IN;
+        const int64_t si = s0 + row;
+        float v = 0.0f;
+        if (c < NFEAT && si < n) v = (x[si * NFEAT + c] - norm[c]) / norm[6 + c];
+        act[0][row * APITCH + c] = (__bf16)v;
+    }
+    __syncthreads();
+    // hidden layer: wave w computes output features 64 w .. 64 w + 63 of all
+    // FS samples as the transposed product (weights as the MFMA's first
+    // operand), so each lane holds runs of 4 consecutive features of one
+    // sample and writes them to LDS as one 8-byte store
+    auto hidden = [&](const __bf16* __restrict__ W, const float* __restrict__ bias, int K,
+                      const __bf16* in, __bf16* out) {
+        const int n0 = 64 * wave;
+        f32x16 acc[2][2] = {};  // [feature tile][sample tile]
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            bf16x8 w[2], a[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                w[i] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + 32 * i + r) * K + k0 + kh);
+                a[i] = *reinterpret_cast<const bf16x8*>(in + (32 * i + r) * APITCH + k0 + kh);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], a[j], acc[i][j], 0, 0, 0);
+        }
+        using bf16x4 = __bf16 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int nf = n0 + 32 * i + 8 * g + 4 * (lane >> 5);  // features nf .. nf + 3
+                const float4 bc = *reinterpret_cast<const float4*>(bias + nf);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    bf16x4 o;
+                    o[0] = (__bf16)silu(acc[i][j][4 * g + 0] + bc.x);
+                    o[1] = (__bf16)silu(acc[i][j][4 * g + 1] + bc.y);
+                    o[2] = (__bf16)silu(acc[i][j][4 * g + 2] + bc.z);
+                    o[3] = (__bf16)silu(acc[i][j][4 * g + 3] + bc.w);
+                    *reinterpret_cast<bf16x4*>(out + (32 * j + r) * APITCH + nf) = o;
+                }
+            }
+    };
+    hidden(W0, b0, PAD_IN, act[0], act[1]);
+    __syncthreads();
+    hidden(W1, b1, WIDTH, act[1], act[0]);
+    __syncthreads();
+    hidden(W2, b2, WIDTH, act[0], act[1]);
+    __syncthreads();
+    // output layer (PAD_OUT features, feature 0 is the network's output), also
+    // transposed: waves 0 and 1 take samples 0-31 and 32-63; feature 0 of
+    // sample 32 w + r sits in element 0 of lane r
+    if (wave < 2) {
+        f32x16 acc = {};
+#pragma unroll 4
+        for (int k0 = 0; k0 < WIDTH; k0 += 16) {
+            const bf16x8 w = *reinterpret_cast<const bf16x8*>(W3 + (size_t)r * WIDTH + k0 + kh);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(act[1] + (32 * wave + r) * APITCH + k0 + kh);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a, acc, 0, 0, 0);
+        }
+        const int64_t si = s0 + 32 * wave + r;
+        if (lane < 32 && si < n) y[si] = norm[12] + norm[13] * (acc[0] + b3[0]);
     }
 }
 
@@ -122,13 +287,24 @@ __global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict
     }
 }
 
-// db[n] = sum_b dZ[b][n] (fixed order).
-__global__ void k_bias_grad(const __bf16* __restrict__ dZ, int B, int N, float* __restrict__ db) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// db[n] = sum_b dZ[b][n] in a fixed order: a block of 1024 threads takes 32
+// columns; thread (g, c) sums rows g, g + 32, ... of its column, then the 32
+// partials of a column are added in order of g.
+__global__ void __launch_bounds__(1024) k_bias_grad(const __bf16* __restrict__ dZ, int B, int N,
+                                                   float* __restrict__ db) {
+    __shared__ float part[32][33];
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int n = blockIdx.x * 32 + c;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += (float)dZ[(size_t)b * N + n];
-    db[n] = s;
+    if (n < N)
+        for (int b = g; b < B; b += 32) s += (float)dZ[(size_t)b * N + n];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float a = 0.0f;
+        for (int i = 0; i < 32; ++i) a += part[i][c];
+        db[n] = a;
+    }
 }
 
 // Adam on the fp32 master copy (only the unpadded parameters move), then
@@ -254,17 +430,28 @@ __global__ void k_sum(const float* __restrict__ v, int n, float* __restrict__ ou
 
 static unsigned gemm_blocks(int M, int N) { return (unsigned)(((M / 32) * (N / 32) + 3) / 4); }
 
+// The LDS-tiled kernel where the shape allows it and gives at least 128
+// blocks (large batches), the per-wave one otherwise (at batch 1024 the
+// per-wave kernel's 64 blocks beat the tiled kernel's 16).
+template <bool a_km, bool b_nk, int epi>
+static void gemm(const __bf16* A, int lda, const __bf16* B, int ldb, int M, int N, int K, const float* bias,
+                 const float* aux, float* out0, __bf16* out1, hipStream_t s) {
+    if (M % TBM == 0 && N % TBN == 0 && K % TBK == 0 && (M / TBM) * (N / TBN) >= 128)
+        k_gemm_lds<a_km, b_nk, epi><<<(unsigned)((M / TBM) * (N / TBN)), 256, 0, s>>>(A, lda, B, ldb, M, N, K, bias,
+                                                                                     aux, out0, out1);
+    else
+        k_gemm<a_km, b_nk, epi><<<gemm_blocks(M, N), 256, 0, s>>>(A, lda, B, ldb, M, N, K, bias, aux, out0, out1);
+}
+
 // Forward pass over a batch of B (multiple of 32) packed inputs in h->xb.
 static void forward(lbmp_sg* h, int B, hipStream_t s) {
     const __bf16* A = h->xb;
     for (int l = 0; l < NLAYER; ++l) {
         const int N = lout(l), K = lin(l);
         if (l < NLAYER - 1)
-            k_gemm<true, true, EPI_HIDDEN><<<gemm_blocks(B, N), 256, 0, s>>>(
-                A, K, h->L[l].Wb, K, B, N, K, h->L[l].b, nullptr, h->Z[l], h->Ab[l]);
+            gemm<true, true, EPI_HIDDEN>(A, K, h->L[l].Wb, K, B, N, K, h->L[l].b, nullptr, h->Z[l], h->Ab[l], s);
         else
-            k_gemm<true, true, EPI_OUT><<<gemm_blocks(B, N), 256, 0, s>>>(
-                A, K, h->L[l].Wb, K, B, N, K, h->L[l].b, nullptr, h->Z[l], nullptr);
+            gemm<true, true, EPI_OUT>(A, K, h->L[l].Wb, K, B, N, K, h->L[l].b, nullptr, h->Z[l], nullptr, s);
         A = h->Ab[l];
     }
 }
@@ -276,13 +463,12 @@ static void backward(lbmp_sg* h, int B, hipStream_t s) {
         const int O = lout(l), I = lin(l);
         const __bf16* Aprev = l == 0 ? h->xb : h->Ab[l - 1];
         // dW[o][i] = sum_b dZ[b][o] A[b][i]
-        k_gemm<false, false, EPI_GRAD><<<gemm_blocks(O, I), 256, 0, s>>>(
-            h->dZb[l], O, Aprev, I, O, I, B, nullptr, nullptr, h->L[l].gW, nullptr);
-        k_bias_grad<<<(O + 255) / 256, 256, 0, s>>>(h->dZb[l], B, O, h->L[l].gb);
+        gemm<false, false, EPI_GRAD>(h->dZb[l], O, Aprev, I, O, I, B, nullptr, nullptr, h->L[l].gW, nullptr, s);
+        k_bias_grad<<<(O + 31) / 32, 1024, 0, s>>>(h->dZb[l], B, O, h->L[l].gb);
         if (l > 0) {
             // dA[b][i] = sum_o dZ[b][o] W[o][i]; W^T stored [i][o]
-            k_gemm<true, true, EPI_DACT><<<gemm_blocks(B, I), 256, 0, s>>>(
-                h->dZb[l], O, h->L[l].WTb, O, B, I, O, nullptr, h->Z[l - 1], nullptr, h->dZb[l - 1]);
+            gemm<true, true, EPI_DACT>(h->dZb[l], O, h->L[l].WTb, O, B, I, O, nullptr, h->Z[l - 1], nullptr,
+                                       h->dZb[l - 1], s);
         }
     }
 }
@@ -522,13 +708,11 @@ extern "C" lbmp_status sg_predict(lbmp_sg* h, const float* x_dev, int64_t n, flo
     if (st != LBMP_OK) return st;
     if (n < 0 || (n > 0 && (!x_dev || !y_dev))) return fail(LBMP_EINVAL, "bad arguments");
     hipStream_t s = h->stream;
-    for (int64_t o = 0; o < n; o += h->bmax) {
-        const int B = (int)std::min<int64_t>(h->bmax, n - o);
-        const int Bp = (B + 31) / 32 * 32;
-        k_gather<<<(B + 255) / 256, 256, 0, s>>>(x_dev + o * NFEAT, nullptr, nullptr, B, h->norm, h->xg, nullptr);
-        k_pack_input<<<(Bp * PAD_IN + 255) / 256, 256, 0, s>>>(h->xg, Bp, h->xb);
-        forward(h, Bp, s);
-        k_denorm<<<(B + 255) / 256, 256, 0, s>>>(h->Z[NLAYER - 1], B, h->norm, y_dev + o);
+    if (n > 0) {
+        const Layer* L = h->L;
+        k_mlp_forward<<<(unsigned)((n + FS - 1) / FS), 256, 0, s>>>(x_dev, n, h->norm, L[0].Wb, L[0].b, L[1].Wb,
+                                                                    L[1].b, L[2].Wb, L[2].b, L[3].Wb, L[3].b,
+                                                                    y_dev);
     }
     LBMP_HIP(hipGetLastError());
     return LBMP_OK;

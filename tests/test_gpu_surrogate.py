@@ -79,11 +79,12 @@ def test_predict_ragged_and_normalisation(lb):
     sg.free()
 
 
-def test_gradients_match_reference(lb):
+@pytest.mark.parametrize("B", [512, 8192])
+def test_gradients_match_reference(lb, B):
+    """Batch 8192 runs the hidden-layer GEMMs on the LDS-tiled kernel."""
     import torch
     params = mlp.init_params(7)
     rng = np.random.default_rng(3)
-    B = 512
     x = rng.normal(size=(B, 6))
     t = np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2]
     sg = lb.Surrogate(B, seed=0)
@@ -94,6 +95,28 @@ def test_gradients_match_reference(lb):
     assert abs(loss / lref - 1) < 2e-2
     for a, b in zip(unflat(g, params), gref):
         assert rel(a, b) < 2e-2
+
+
+def test_fused_predict_equals_layer_path(lb):
+    """The fused inference kernel and the layer-by-layer forward of training
+    do the same arithmetic: the loss from fused predictions equals the loss
+    the training path reports (up to the order of the final mean)."""
+    import torch
+    params = mlp.init_params(8)
+    rng = np.random.default_rng(4)
+    B = 1024
+    x = rng.normal(size=(B, 6))
+    t = np.cos(x[:, 1]) - 0.2 * x[:, 3]
+    sg = lb.Surrogate(B, seed=0)
+    sg.set_params(flat(params))
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    _, loss = sg.gradients(xt, tt, B)
+    y = sg.predict(xt)
+    sg.sync()
+    lf = float(((y - tt) ** 2).double().mean())
+    assert abs(lf / loss - 1) < 1e-5
+    sg.free()
 
 
 def test_training_fits_smooth_function(lb):
