@@ -239,7 +239,10 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--save-data", metavar="NPZ", help="write the generated rows (and timings) to NPZ")
-    ap.add_argument("--load-data", metavar="NPZ", help="train and evaluate on rows from NPZ, no generation")
+    ap.add_argument("--generate-only", action="store_true", help="stop after generating (and saving) the rows")
+    ap.add_argument("--load-data", metavar="NPZ", nargs="+",
+                    help="train and evaluate on the rows of one or more NPZ files (parts generated with "
+                         "disjoint seeds are concatenated), no generation")
     args = ap.parse_args(argv)
     from . import lbmp
     lbmp.load_library()
@@ -248,10 +251,16 @@ def main(argv=None):
         print(*a, file=sys.stderr, flush=True)
 
     if args.load_data:
-        d = np.load(args.load_data)
-        Xtr, Ytr, Xte, Yte = d["Xtr"], d["Ytr"], d["Xte"], d["Yte"]
-        t_gen, plain_s, answered = float(d["t_gen"]), float(d["plain_s"]), int(d["answered"])
-        args.train_groups, args.test_groups = int(d["train_groups"]), int(d["test_groups"])
+        parts = [np.load(f) for f in args.load_data]
+        Xtr = np.concatenate([d["Xtr"] for d in parts])
+        Ytr = np.concatenate([d["Ytr"] for d in parts])
+        Xte = np.concatenate([d["Xte"] for d in parts])
+        Yte = np.concatenate([d["Yte"] for d in parts])
+        t_gen = sum(float(d["t_gen"]) for d in parts)
+        plain_s = sum(float(d["plain_s"]) for d in parts)
+        answered = sum(int(d["answered"]) for d in parts)
+        args.train_groups = sum(int(d["train_groups"]) for d in parts)
+        args.test_groups = sum(int(d["test_groups"]) for d in parts)
     else:
         t0 = time.time()
         Xtr, Ytr = [], []
@@ -271,10 +280,17 @@ def main(argv=None):
             Xte.append(x)
             Yte.append(y)
             answered += len(y)
-        Xte, Yte = np.concatenate(Xte), np.concatenate(Yte)
+        Xte = np.concatenate(Xte) if Xte else np.zeros((0, Xtr.shape[1]))
+        Yte = np.concatenate(Yte) if Yte else np.zeros(0)
         if args.save_data:
             np.savez(args.save_data, Xtr=Xtr, Ytr=Ytr, Xte=Xte, Yte=Yte, t_gen=t_gen, plain_s=plain_s,
                      answered=answered, train_groups=args.train_groups, test_groups=args.test_groups)
+        if args.generate_only:
+            print(json.dumps({"train_rows": int(len(Ytr)), "test_rows": int(len(Yte)), "generation_s": t_gen,
+                              "plain_s": plain_s, "answered": answered}), flush=True)
+            return
+    if len(Yte) == 0:
+        raise SystemExit("no held-out rows to evaluate on")
     t1 = time.time()
     sg, losses = train(lbmp, Xtr, Ytr, epochs=args.epochs, seed=args.seed, log=log)
     sg.sync()
