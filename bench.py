@@ -67,23 +67,29 @@ def build_porous(lb):
     return [fl], [sp], [f], [n]
 
 
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "mp_step_traffic.json")
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip"), "rb").read()).hexdigest()
+
+
 def traffic_record(tile: str):
     """Measured HBM bytes per launch of the propagation kernel, if taken on the
     current kernel source with the same tile choice ("variant,K,species per
-    block") as this run (profiles/mp_step_traffic.json)."""
-    path = os.path.join(ROOT, "profiles", "mp_step_traffic.json")
-    src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
-    if not os.path.exists(path):
+    block") as this run (profiles/mp_step_traffic.json holds one entry per
+    measured tile)."""
+    if not os.path.exists(TRAFFIC_PATH):
         return None
-    rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha or rec.get("tile") != tile:
+    rec = json.load(open(TRAFFIC_PATH))
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    ent = rec.get("tiles", {}).get(tile)
+    return ent.get("bytes_per_launch") if ent else None
 
 
 KERNELS = {0: ("direct", "k_mp_step"), 1: ("lds-box", "k_mp_step_box"), 2: ("z-march", "k_mp_march"),
-           3: ("lds-dma", "k_mp_dma")}
+           3: ("lds-dma", "k_mp_dma"), 4: ("lds-dma-zpair", "k_mp_dma")}
 
 
 def rocprof_summary(root: str) -> dict:
@@ -128,9 +134,7 @@ def traffic_from_counters(root: str, copy_bytes: int) -> dict:
     cw = [v["WRITE_SIZE"]["median"] for k, v in summ.items() if "k_mp" not in k and "WRITE_SIZE" in v]
     f_scale = copy_bytes / (max(cf) * 1024.0)
     w_scale = copy_bytes / (max(cw) * 1024.0)
-    src = os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip")
-    return {"kernel": "k_mp_dma", "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
-            "tile": os.environ.get("LBMP_TILE"),
+    return {"kernel": "k_mp_dma", "tile": os.environ.get("LBMP_TILE"),
             "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
             "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
             "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale}
@@ -247,10 +251,16 @@ def main():
         print(json.dumps(rocprof_summary(args.rocprof_summary), indent=1))
         return
     if args.traffic_record:
-        rec = traffic_from_counters(args.traffic_record, 1024 << 20)
-        with open(os.path.join(ROOT, "profiles", "mp_step_traffic.json"), "w") as fh:
+        # one entry per tile (LBMP_TILE of the counter runs); entries of an
+        # older kernel source are dropped
+        ent = traffic_from_counters(args.traffic_record, 1024 << 20)
+        rec = json.load(open(TRAFFIC_PATH)) if os.path.exists(TRAFFIC_PATH) else {}
+        if rec.get("kernel_source_sha256") != kernel_source_sha():
+            rec = {"kernel": "k_mp_dma", "kernel_source_sha256": kernel_source_sha(), "tiles": {}}
+        rec["tiles"][ent["tile"]] = ent
+        with open(TRAFFIC_PATH, "w") as fh:
             json.dump(rec, fh, indent=1)
-        print(json.dumps(rec))
+        print(json.dumps(ent))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the batched workload is one GPU's share "
@@ -339,7 +349,7 @@ def main():
                             "variant": KERNELS[st["kernel_variant"]][0]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic if st["kernel_variant"] == 3 else None,
+                     "traffic": traffic if st["kernel_variant"] in (3, 4) else None,
                      "kernel": KERNELS[st["kernel_variant"]][1], "kernel_avg_ms": k_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg},
         "mass_error_max": mass_err,

@@ -716,22 +716,25 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // z-neighbour, and the blocks that share a tile's link data, are resident
 // together. Waves without an interface node skip the sorption arithmetic.
 constexpr int RX = TX + 2;                       // haloed row
-template <int NH>
+// NH reduction tiles per block, stacked along y (ZX false: a TX x NH TY tile
+// of one plane) or along z (ZX true: a TX x TY tile of NH consecutive planes)
+template <int NH, bool ZX>
 struct DmaShape {
-    static constexpr int DTY = NH * TY, DBLK = NH * BLK;  // block tile rows, threads
+    static constexpr int DTY = ZX ? TY : NH * TY, DBLK = NH * BLK;  // block tile rows, threads
+    static constexpr int NPL = ZX ? NH + 2 : 3;            // planes in the region
     static constexpr int RPL = RX * (DTY + 2);            // one haloed plane
-    static constexpr int RREG = 3 * RPL;                  // planes z-1, z, z+1
+    static constexpr int RREG = NPL * RPL;                // planes z0-1 .. z0+NPL-2
     static constexpr int RLD = (RREG + DBLK - 1) / DBLK;  // region loads per thread and field
+    // Region layout: row-interleaved planes, element (hy, pz, hx) at
+    // (NPL hy + pz) RX + hx, so the 19 stencil values of a node lie within
+    // (2 NPL + 2) RX + 3 dwords of its (x-1, y-1, z-1) corner.
+    __host__ __device__ static constexpr int at(int hy, int pz, int hx) { return (NPL * hy + pz) * RX + hx; }
     static constexpr int STAGE = (RLD + 1) * DBLK;        // dwords: region, then adsorbed values
     // vector-memory operations a wave issues after a field's copy, up to the
     // wait for it: the copies of the next two fields and the stores of the
     // two before (with and without interface nodes in the wave)
     static constexpr int WAIT_I = 2 * (RLD + 1) + 2 * 2, WAIT_N = 2 * RLD + 2;
 };
-// Region layout: row-interleaved planes, element (hy, pz, hx) at
-// (3 hy + pz) RX + hx, so the 19 stencil values of a node lie within 530
-// dwords of its (x-1, y-1, z-1) corner.
-__host__ __device__ constexpr int region_at(int hy, int pz, int hx) { return (3 * hy + pz) * RX + hx; }
 constexpr int DMA_GMAX = 64;                     // species per block
 constexpr int NSUM = 5;                          // per-node block sums of a species
 
@@ -783,10 +786,10 @@ struct Stages {
     __device__ __forceinline__ float* at() const { return p[Q]; }
 };
 
-template <int NH>
+template <int NH, bool ZX>
 __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
                                                int64_t nblocks, const Ctl* __restrict__ ctl) {
-    using SH = DmaShape<NH>;
+    using SH = DmaShape<NH, ZX>;
     constexpr int DTY = SH::DTY, DBLK = SH::DBLK, RREG = SH::RREG, RLD = SH::RLD, STAGE = SH::STAGE;
     __shared__ __align__(16) float st0[STAGE];
     __shared__ __align__(16) float st1[STAGE];
@@ -803,17 +806,19 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int64_t btile = local / G.ngrp;  // block tile; reduction tiles NH btile + half
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int ntx = (nx + TX - 1) / TX;
-    const int z = (int)(btile % nz);
-    const int64_t cxy = btile / nz;
+    const int nzb = ZX ? (nz + NH - 1) / NH : nz;  // block positions along z
+    const int z0 = (int)(btile % nzb) * (ZX ? NH : 1);
+    const int64_t cxy = btile / nzb;
     const int x0 = (int)(cxy % ntx) * TX, y0 = (int)(cxy / ntx) * DTY;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int tid = threadIdx.x, lx = tid % TX;
+    const int ly = ZX ? (tid / TX) % TY : tid / TX, zp = ZX ? tid / BLK : 0;  // row, plane in the block
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
     const int hf = wv >> 2, w4 = wv & 3;        // half of the block, wave within it
     const int64_t tile = NH * btile + hf;       // this wave's reduction tile
-    const int x = x0 + lx, y = y0 + ly;
-    const bool inplane = x < nx && y < ny;
+    const int x = x0 + lx, y = y0 + ly, z = z0 + zp;
+    const bool inplane = x < nx && y < ny && z < nz;
     const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
-    const int n = z * plane + (inplane ? y * nx + x : 0);
+    const int n = inplane ? z * plane + y * nx + x : 0;
     const bool act = inplane && G.cls[n] != 0;
     const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
     const int64_t ntile = G.ntile;
@@ -835,8 +840,8 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int j = 0; j < RLD; ++j) {
         const int e = j * DBLK + tid;
-        const int hy = e / (3 * RX), pz = (e / RX) % 3, hx = e % RX;
-        const int m = e < RREG ? modp(z - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
+        const int hy = e / (SH::NPL * RX), pz = (e / RX) % SH::NPL, hx = e % RX;
+        const int m = e < RREG ? modp(z0 - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
         voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
     }
     double pin[NL];
@@ -948,7 +953,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
     };
 
-    const int cb = region_at(ly, 0, lx);  // region index of (x-1, y-1, z-1)
+    const int cb = SH::at(ly, zp, lx);  // region index of (x-1, y-1, z-1)
     int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -1013,10 +1018,10 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
                 // all 19 values first (the node's own first: the chain starts
                 // with it), then the arithmetic
-                const double xc = (double)sb[region_at(1, 1, 1)];
+                const double xc = (double)sb[SH::at(1, 1, 1)];
                 float v[NL];
 #pragma unroll
-                for (int k = 0; k < NL; ++k) v[k] = sb[region_at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
                 double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
                 acc0 = __builtin_fma(cq[q], src, acc0);
 #pragma unroll
@@ -1365,6 +1370,8 @@ int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
     // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
     if (variant == 3) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + K * TY - 1) / (K * TY)) * f->nz;
+    // variant 4: K reduction tiles (TX x TY) per block of K planes
+    if (variant == 4) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * ((f->nz + K - 1) / K);
     if (variant >= 1) return (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * zb;
     return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
@@ -1461,7 +1468,7 @@ lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species,
         g.NI = g.flow->ni;
         g.nf = g.flow->nf;
         g.ntile_max = std::max({ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1), ntile_for(g.flow, 1, 3),
-                                ntile_for(g.flow, 2, 3)});
+                                ntile_for(g.flow, 2, 3), ntile_for(g.flow, 2, 4)});
     }
     return h;
 }
@@ -1470,10 +1477,11 @@ template <typename T>
 void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     dim3 grid((unsigned)h->nblocks);
-    if (h->variant == 3) {
+    if (h->variant == 3 || h->variant == 4) {
         if constexpr (std::is_same<T, float>::value) {
-            if (h->K == 2) k_mp_dma<2><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
-            else k_mp_dma<1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            if (h->variant == 4) k_mp_dma<2, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->K == 2) k_mp_dma<2, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else k_mp_dma<1, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
         }
         return;
     }
@@ -1534,7 +1542,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
         d.ntile = ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += (h->variant == 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variant 3: one block per K tiles
+        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3, 4: one block per K tiles
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -1591,7 +1599,8 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        const bool ok3 = v == 3 && (K == 1 || K == 2) && gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
+        const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || (v == 4 && K == 2)) && gs >= 1 && gs <= DMA_GMAX &&
+                         h->prec == LBMP_FP32 && dma_fits(h);
         if (nread == 3 && (ok01 || ok2 || ok3)) {
             h->variant = v;
             h->K = K;
@@ -1600,7 +1609,8 @@ lbmp_status autotune(lbmp_mp* h) {
         }
         return fail(LBMP_EINVAL, "LBMP_TILE must be 'variant,K,species_per_block': variant 0|1 with K 1|2, "
                                  "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
-                                 "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles) and at most 64 species per block");
+                                 "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles), or variant 4 (FP32 only) with K = 2 "
+                                 "(z-planes per block); at most 64 species per block for 3 and 4");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1629,8 +1639,10 @@ lbmp_status autotune(lbmp_mp* h) {
                 cand.push_back({zs, gs, 2});
     if (h->prec == LBMP_FP32 && dma_fits(h))
         for (int gs : {2, 4, 8, 16, 32, 64})
-            for (int K : {1, 2})
+            for (int K : {1, 2}) {
                 if (gs <= maxS || gs == 2) cand.push_back({K, gs, 3});
+                if (K == 2 && (gs <= maxS || gs == 2)) cand.push_back({K, gs, 4});
+            }
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
     LBMP_HIP(hipEventCreate(&e1));

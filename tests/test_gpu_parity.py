@@ -171,7 +171,8 @@ def test_poiseuille_c2_full_length_fp32(lb, pe):
 
 
 @pytest.mark.parametrize("tile", ["0,1,1", "0,2,3", "1,1,2", "1,2,5", "1,2,8", "2,8,1", "2,3,2", "2,16,4", "2,2,4",
-                                  "3,1,1", "3,1,2", "3,1,5", "3,2,1", "3,2,3", "3,2,5"])
+                                  "3,1,1", "3,1,2", "3,1,5", "3,2,1", "3,2,3", "3,2,5", "4,2,1", "4,2,3",
+                                  "4,2,5"])
 @pytest.mark.parametrize("prec", [64, 32])
 def test_kernel_variants(lb, monkeypatch, tile, prec):
     """Every step-kernel variant (direct / LDS-staged / z-march / LDS DMA, K
@@ -186,7 +187,7 @@ def test_kernel_variants(lb, monkeypatch, tile, prec):
     T = 150
     flow = lb.lb_flow_from_velocity(m, u)
     v, K, gs = (int(c) for c in tile.split(","))
-    if v == 3 and prec == 64:
+    if v in (3, 4) and prec == 64:
         with pytest.raises(lb.LbmpError) as e:
             lb.mp_init(flow, {"D_b": 0.06, "k_a": ka, "k_d": kd}, prec, T)
         assert e.value.status == -1
@@ -204,20 +205,20 @@ def test_kernel_variants(lb, monkeypatch, tile, prec):
     mp.free()
 
 
-@pytest.mark.parametrize("K,gs", [(1, 1), (1, 3), (2, 1), (2, 3)])
-def test_dma_variant_slit_mixed_waves(lb, monkeypatch, K, gs):
-    """LDS DMA variant (blocks of 64 x 4 K nodes) on a slit with flow along x
-    (64 x 8 x 22): waves of the wall-adjacent planes carry sorption, waves of
-    the bulk planes skip it. Three species over 400 FP32 steps vs the full 3D
-    oracle."""
-    monkeypatch.setenv("LBMP_TILE", f"3,{K},{gs}")
+@pytest.mark.parametrize("tile", ["3,1,1", "3,1,3", "3,2,1", "3,2,3", "4,2,1", "4,2,3"])
+def test_dma_variant_slit_mixed_waves(lb, monkeypatch, tile):
+    """LDS DMA variants (blocks of 64 x 4 K nodes of one plane, or of 64 x 4
+    nodes on 2 planes) on a slit with flow along x (64 x 8 x 22): waves of the
+    wall-adjacent planes carry sorption, waves of the bulk planes skip it.
+    Three species over 400 FP32 steps vs the full 3D oracle."""
+    monkeypatch.setenv("LBMP_TILE", tile)
     m = inputs.slit_mask(64, 8, 22)
     u = inputs.random_velocity(m, 0.02, seed=40)
     ka, kd = np.array([0.02, 0.0, 0.3]), np.array([0.01, 0.2, 0.6])
     T = 400
     flow = lb.lb_flow_from_velocity(m, u)
     mp = lb.mp_init(flow, {"D_b": 0.05, "k_a": ka, "k_d": kd}, 32, T)
-    assert lb.mp_stats(mp, 0)["kernel_variant"] == 3
+    assert lb.mp_stats(mp, 0)["kernel_variant"] == int(tile[0])
     lb.mp_step_n(mp, T)
     out = lb.mp_vacf(mp, 0)
     for s in range(3):
