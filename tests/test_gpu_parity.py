@@ -205,6 +205,35 @@ def test_kernel_variants(lb, monkeypatch, tile, prec):
     mp.free()
 
 
+@pytest.mark.parametrize("tile", ["3,1,64", "3,2,64", "4,2,64"])
+def test_dma_variant_full_species_groups(lb, monkeypatch, tile):
+    """LDS-DMA variants at the largest species group (64 per block): 66
+    species on the ragged porous lattice, one full group and one of 2, every
+    species against the oracle."""
+    monkeypatch.setenv("LBMP_TILE", tile)
+    m = inputs.random_mask(70, 9, 7, 0.3, seed=23)
+    u = inputs.random_velocity(m, 0.02, seed=24)
+    ka, kd = inputs.loguniform_rates(66, 1e-3, 3e-1, seed=25)
+    T = 120
+    flow = lb.lb_flow_from_velocity(m, u)
+    mp = lb.mp_init(flow, {"D_b": 0.06, "k_a": ka, "k_d": kd}, 32, T)
+    st = lb.mp_stats(mp, 0)
+    assert (st["kernel_variant"], st["species_per_block"]) == (int(tile[0]), 64)
+    lb.mp_step_n(mp, T)
+    out = lb.mp_vacf(mp, 0)
+    for s in range(66):
+        if s not in _GROUP_REFS:   # the oracle once per species for all tiles
+            ref = oracle.vacf(m, u, 0.72, ka[s], kd[s], T)
+            _GROUP_REFS[s] = (oracle.d_of_t(ref["Z"], ref["V"]), ref["mass"][:, -1])
+        Dref, mref = _GROUP_REFS[s]
+        assert d_err(out["D"][s], Dref, 0.06, 32) < 1e-5, s
+        assert np.allclose(out["mass"][s], mref, rtol=1e-5)
+    mp.free()
+
+
+_GROUP_REFS = {}
+
+
 @pytest.mark.parametrize("tile", ["3,1,1", "3,1,3", "3,2,1", "3,2,3", "4,2,1", "4,2,3"])
 def test_dma_variant_slit_mixed_waves(lb, monkeypatch, tile):
     """LDS DMA variants (blocks of 64 x 4 K nodes of one plane, or of 64 x 4
