@@ -54,8 +54,12 @@ def run(lb, steps: int, per_decade: int = 10, precision: int = 32, log=None, **k
     import torch
     torch.cuda.synchronize()
     t0 = time.time()
-    lb.mp_step_n(mp, steps)
-    mp.stream.synchronize()
+    chunk = 10000  # report progress every chunk of steps
+    for done in range(0, steps, chunk):
+        lb.mp_step_n(mp, min(chunk, steps - done))
+        mp.stream.synchronize()
+        if log:
+            log(f"steps {min(done + chunk, steps)}/{steps}: {time.time() - t0:.1f}s")
     el = time.time() - t0
     out = lb.mp_vacf(mp, 0, 0, steps + 1)
     grid = log_grid(steps, per_decade)
