@@ -89,7 +89,8 @@ def traffic_record(tile: str):
 
 
 KERNELS = {0: ("direct", "k_mp_step"), 1: ("lds-box", "k_mp_step_box"), 2: ("z-march", "k_mp_march"),
-           3: ("lds-dma", "k_mp_dma"), 4: ("lds-dma-zpair", "k_mp_dma")}
+           3: ("lds-dma", "k_mp_dma"), 4: ("lds-dma-zpair", "k_mp_dma"),
+           5: ("lds-dma-rows", "k_mp_dma"), 6: ("lds-dma-zpair-rows", "k_mp_dma")}
 
 
 def rocprof_summary(root: str) -> dict:
@@ -349,7 +350,7 @@ def main():
                             "variant": KERNELS[st["kernel_variant"]][0]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic if st["kernel_variant"] in (3, 4) else None,
+                     "traffic": traffic if st["kernel_variant"] >= 3 else None,
                      "kernel": KERNELS[st["kernel_variant"]][1], "kernel_avg_ms": k_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg},
         "mass_error_max": mass_err,

@@ -717,28 +717,45 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // together. Waves without an interface node skip the sorption arithmetic.
 constexpr int RX = TX + 2;                       // haloed row
 // NH reduction tiles per block, stacked along y (ZX false: a TX x NH TY tile
-// of one plane) or along z (ZX true: a TX x TY tile of NH consecutive planes)
-template <int NH, bool ZX>
+// of one plane) or along z (ZX true: a TX x TY tile of NH consecutive planes).
+// FR (full rows, lattices with nx = TX): the tile spans whole periodic rows,
+// so the region has no x halo (x +- 1 wraps inside the row) and is copied in
+// groups of 4 rows, one 16-byte copy per lane (lane i of a wave fills dwords
+// 4i .. 4i+3 of the wave's destination).
+template <int NH, bool ZX, bool FR = false>
 struct DmaShape {
     static constexpr int DTY = ZX ? TY : NH * TY, DBLK = NH * BLK;  // block tile rows, threads
     static constexpr int NPL = ZX ? NH + 2 : 3;            // planes in the region
-    static constexpr int RPL = RX * (DTY + 2);            // one haloed plane
-    static constexpr int RREG = NPL * RPL;                // planes z0-1 .. z0+NPL-2
-    static constexpr int RLD = (RREG + DBLK - 1) / DBLK;  // region loads per thread and field
+    static constexpr int RXS = FR ? TX : RX;              // region row length
+    static constexpr int RROWS = NPL * (DTY + 2);         // region rows
+    static constexpr int RREG = RROWS * RXS;              // planes z0-1 .. z0+NPL-2
+    static constexpr int RLD = (RREG + DBLK - 1) / DBLK;  // 4-byte region loads per thread and field
+    static constexpr int NW = DBLK / 64;                  // waves
+    static constexpr int CPW = (RROWS + 4 * NW - 1) / (4 * NW);  // 16-byte row-group loads per wave and field
+    static constexpr int NCP = FR ? CPW : RLD;            // region copies a wave issues per field
+    // region dwords of a stage (FR: 4-row groups of every wave, the last ones
+    // partly or wholly padding), then the adsorbed values of the tile
+    static constexpr int REGION = FR ? NW * CPW * 4 * TX : RLD * DBLK;
+    static constexpr int STAGE = REGION + DBLK;
     // Region layout: row-interleaved planes, element (hy, pz, hx) at
-    // (NPL hy + pz) RX + hx, so the 19 stencil values of a node lie within
-    // (2 NPL + 2) RX + 3 dwords of its (x-1, y-1, z-1) corner.
-    __host__ __device__ static constexpr int at(int hy, int pz, int hx) { return (NPL * hy + pz) * RX + hx; }
-    static constexpr int STAGE = (RLD + 1) * DBLK;        // dwords: region, then adsorbed values
+    // (NPL hy + pz) RXS + hx, so the 19 stencil values of a node lie within
+    // (2 NPL + 2) RXS + 3 dwords of its (x-1, y-1, z-1) corner.
+    __host__ __device__ static constexpr int at(int hy, int pz, int hx) { return (NPL * hy + pz) * RXS + hx; }
     // vector-memory operations a wave issues after a field's copy, up to the
     // wait for it: the copies of the next two fields and the stores of the
     // two before (with and without interface nodes in the wave)
-    static constexpr int WAIT_I = 2 * (RLD + 1) + 2 * 2, WAIT_N = 2 * RLD + 2;
+    static constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2;
 };
 constexpr int DMA_GMAX = 64;                     // species per block
 constexpr int NSUM = 5;                          // per-node block sums of a species
 
 #define LBMP_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// 16-byte LDS-DMA copy: lane i fills dwords 4i .. 4i+3 from dst. (Outside the
+// kernel template: inside one, the host pass silently drops the launch stub.)
+__device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t r, float* dst, int voff, int soff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, LBMP_LDS(dst), 16, voff, soff, 0, 0);
+}
 // s_waitcnt immediate: vmcnt(c), no expcnt wait, lgkmcnt(0)
 #define LBMP_WAIT_VM_LGKM0(c) __builtin_amdgcn_s_waitcnt(((c) & 15) | ((((c) >> 4) & 3) << 14) | 0x0070)
 
@@ -770,6 +787,22 @@ __device__ __forceinline__ double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
+// Rotation of a wave by one lane: lane i receives lane i - 1 (ROR1) or i + 1
+// (ROL1), mod 64.
+constexpr int DPP_WAVE_ROL1 = 0x134, DPP_WAVE_ROR1 = 0x13C;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+// The x-centred link of the row a link with an x component reads from (same
+// y and z components), -1 for the node's own row.
+__host__ __device__ constexpr int row_link(int k) {
+    for (int j = 0; j < NL; ++j)
+        if (lcx(j) == 0 && lcy(j) == lcy(k) && lcz(j) == lcz(k) && (lcy(k) != 0 || lcz(k) != 0)) return j;
+    return -1;
+}
+static_assert(row_link(0) == -1 && row_link(6) == 2 && row_link(7) == 3 && row_link(12) == 5, "row links");
+
 // Lane 15 of rows 0 and 2 broadcast to rows 1 and 3; rows 0 and 2 receive 0.
 __device__ __forceinline__ double dpp_bcast15(double v) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -786,11 +819,12 @@ struct Stages {
     __device__ __forceinline__ float* at() const { return p[Q]; }
 };
 
-template <int NH, bool ZX>
+template <int NH, bool ZX, bool FR>
 __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
                                                int64_t nblocks, const Ctl* __restrict__ ctl) {
-    using SH = DmaShape<NH, ZX>;
+    using SH = DmaShape<NH, ZX, FR>;
     constexpr int DTY = SH::DTY, DBLK = SH::DBLK, RREG = SH::RREG, RLD = SH::RLD, STAGE = SH::STAGE;
+    constexpr int NCP = SH::NCP, REGION = SH::REGION;
     __shared__ __align__(16) float st0[STAGE];
     __shared__ __align__(16) float st1[STAGE];
     __shared__ __align__(16) float st2[STAGE];
@@ -832,17 +866,28 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
     const int offn = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
-    // this thread's share of the stencil region, element e = j * DBLK + tid
-    int voff[RLD];
+    // this thread's share of the stencil region: element e = j * DBLK + tid,
+    // or (FR) the 4 nodes from x = 4 (lane % 16) of row 4 g + lane / 16,
+    // g = j NW + wave
     // (solid nodes hold zero fields and are never written: their elements are
     // masked like the padding, so the copy fetches fluid nodes only and the
-    // out-of-range lanes write the same zeros)
+    // out-of-range lanes write the same zeros; a 16-byte copy is masked when
+    // its 4 nodes are solid)
+    int voff[NCP];
 #pragma unroll
-    for (int j = 0; j < RLD; ++j) {
-        const int e = j * DBLK + tid;
-        const int hy = e / (SH::NPL * RX), pz = (e / RX) % SH::NPL, hx = e % RX;
-        const int m = e < RREG ? modp(z0 - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
-        voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
+    for (int j = 0; j < NCP; ++j) {
+        if constexpr (FR) {
+            const int r = 4 * (j * SH::NW + wv) + (tid & 63) / 16, hx = 4 * (tid & 15);
+            const int hy = r / SH::NPL, pz = r % SH::NPL;
+            const int m = r < SH::RROWS ? modp(z0 - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + hx : 0;
+            const bool any = r < SH::RROWS && (G.cls[m] | G.cls[m + 1] | G.cls[m + 2] | G.cls[m + 3]) != 0;
+            voff[j] = any ? m * 4 : OOB;
+        } else {
+            const int e = j * DBLK + tid;
+            const int hy = e / (SH::NPL * RX), pz = (e / RX) % SH::NPL, hx = e % RX;
+            const int m = e < RREG ? modp(z0 - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
+            voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
+        }
     }
     double pin[NL];
 #pragma unroll
@@ -881,19 +926,21 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     // base j / GJ at immediate (j % GJ) * DBLK * 4, taken back from its memory
     // offset; the resources start 4 KB below the species so that offset stays
     // non-negative.
-    constexpr int GJ = 4096 / (DBLK * 4);  // copies per LDS base
-    int vo[RLD];
+    constexpr int GJ = FR ? 1 : 4096 / (DBLK * 4);  // copies per LDS base
+    int vo[NCP];
 #pragma unroll
-    for (int j = 0; j < RLD; ++j) vo[j] = voff[j] == OOB ? OOB : voff[j] + 4096 - (j % GJ) * DBLK * 4;
-    const int voa = offa == OOB ? OOB : offa + 4096 - (RLD % GJ) * DBLK * 4;
-    static_assert(RLD <= 5, "copies are unrolled for at most 5 region loads");
+    for (int j = 0; j < NCP; ++j) vo[j] = voff[j] == OOB ? OOB : voff[j] + 4096 - (FR ? 0 : (j % GJ) * DBLK * 4);
+    const int voa = offa == OOB ? OOB : offa + 4096 - (FR ? 0 : (RLD % GJ) * DBLK * 4);
+    static_assert(NCP <= 5, "copies are unrolled for at most 5 region loads");
     auto issue = [&](auto qpc, auto anyc, const float* ib, const float* iab) {
         constexpr int qp = decltype(qpc)::value;  // quantity (and stage) of the copied field
         const auto rin = mkrsrc(reinterpret_cast<const char*>(ib) - 4096, 4 * (int64_t)NB + 4096);
         float* dst = stg.at<qp>() + wv * 64;
         auto copy = [&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            if constexpr (j < RLD)
+            if constexpr (FR && j < NCP)  // row group j NW + wv, 256 dwords
+                lds_copy16(rin, stg.at<qp>() + (j * SH::NW + wv) * 4 * TX, vo[j], qp * NB);
+            else if constexpr (!FR && j < NCP)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + (j / GJ) * GJ * DBLK), 4, vo[j],
                                                          qp * NB, (j % GJ) * DBLK * 4, 0);
         };
@@ -902,10 +949,15 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
         copy(std::integral_constant<int, 2>());
         copy(std::integral_constant<int, 3>());
         copy(std::integral_constant<int, 4>());
-        if constexpr (decltype(anyc)::value)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096),
-                LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa, qp * NIB, (RLD % GJ) * DBLK * 4, 0);
+        if constexpr (decltype(anyc)::value) {
+            const auto rina = mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096);
+            if constexpr (FR)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(stg.at<qp>() + REGION + wv * 64), 4, voa,
+                                                         qp * NIB, 0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa,
+                                                         qp * NIB, (RLD % GJ) * DBLK * 4, 0);
+        }
     };
     // Block sums of a species in a fixed order, one step per field barrier.
     // Per node: the drift-corrected VACF terms X_g (a_g - V_g) - V_g X_ads,g
@@ -953,7 +1005,8 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
     };
 
-    const int cb = SH::at(ly, zp, lx);  // region index of (x-1, y-1, z-1)
+    // region index of (x-1, y-1, z-1); FR: of (x, y-1, z-1)
+    const int cb = SH::at(ly, zp, lx);
     int pend = -1, pend2 = -1;  // species with per-node sums in rl, with partials in l2
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -993,8 +1046,8 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 const int f = 4 * s + q;
                 // field f has landed for the whole block once this wave has at
                 // most the operations issued after it outstanding: the loads of
-                // f+1, f+2 and the stores of f-2, f-1 (2 (RLD + 1) + 2 * 2 with
-                // interface nodes in the wave, 2 RLD + 2 without)
+                // f+1, f+2 and the stores of f-2, f-1 (2 (NCP + 1) + 2 * 2 with
+                // interface nodes in the wave, 2 NCP + 2 without)
                 if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
                 else if constexpr (ANYI) barrier_vm<SH::WAIT_I>();
                 else barrier_vm<SH::WAIT_N>();
@@ -1017,11 +1070,28 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 using lvf = const volatile __attribute__((address_space(3))) float;
                 lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
                 // all 19 values first (the node's own first: the chain starts
-                // with it), then the arithmetic
-                const double xc = (double)sb[SH::at(1, 1, 1)];
-                float v[NL];
+                // with it), then the arithmetic; v[k] is the value at r - c_k
+                float v[NL], c0;
+                if constexpr (FR) {
+                    // a wave is one periodic row (lane = x): the values at x -+ 1
+                    // are the x-centred values of the same row in the lanes
+                    // beside it (a rotation of the wave by one lane)
+                    c0 = sb[SH::at(1, 1, 0)];
 #pragma unroll
-                for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                    for (int k = 0; k < NL; ++k)
+                        if (lcx(k) == 0) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 0)];
+#pragma unroll
+                    for (int k = 0; k < NL; ++k)
+                        if (lcx(k) != 0) {
+                            const float b = row_link(k) < 0 ? c0 : v[row_link(k)];
+                            v[k] = lcx(k) > 0 ? dpp_f32<DPP_WAVE_ROR1>(b) : dpp_f32<DPP_WAVE_ROL1>(b);
+                        }
+                } else {
+                    c0 = sb[SH::at(1, 1, 1)];
+#pragma unroll
+                    for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                }
+                const double xc = (double)c0;
                 double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
                 acc0 = __builtin_fma(cq[q], src, acc0);
 #pragma unroll
@@ -1034,7 +1104,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 if constexpr (q == 0) red[3] += act ? xc : 0.0;
                 else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
                 if constexpr (ANYI) {  // sorption (Eqs. 9, 10) where the wave has interface nodes
-                    const double xa = (double)stg.at<q>()[RLD * DBLK + tid];
+                    const double xa = (double)stg.at<q>()[REGION + tid];
                     const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
                     nvx = (nvx - fa) + fd;
                     bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
@@ -1354,7 +1424,7 @@ struct lbmp_mp {
     double* chunk;   // [nwork][nch_max][NRED] chunk sums of the series reduction
     int nch_max, nch;
     double* setup_tmp;
-    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3: LDS DMA (FP32)
+    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3-6: LDS DMA (FP32)
     int uptake;           // out-of-equilibrium density propagation (no VACF)
     int64_t nblocks;
     hipGraph_t graph = nullptr;
@@ -1369,9 +1439,11 @@ constexpr int GRAPH_CHUNK = 64;
 int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
     // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
-    if (variant == 3) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + K * TY - 1) / (K * TY)) * f->nz;
-    // variant 4: K reduction tiles (TX x TY) per block of K planes
-    if (variant == 4) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * ((f->nz + K - 1) / K);
+    // (variant 5: the same with full rows)
+    if (variant == 3 || variant == 5)
+        return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + K * TY - 1) / (K * TY)) * f->nz;
+    // variant 4 (6: full rows): K reduction tiles (TX x TY) per block of K planes
+    if (variant == 4 || variant == 6) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * ((f->nz + K - 1) / K);
     if (variant >= 1) return (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * zb;
     return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
@@ -1477,11 +1549,13 @@ template <typename T>
 void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     dim3 grid((unsigned)h->nblocks);
-    if (h->variant == 3 || h->variant == 4) {
+    if (h->variant >= 3) {
         if constexpr (std::is_same<T, float>::value) {
-            if (h->variant == 4) k_mp_dma<2, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
-            else if (h->K == 2) k_mp_dma<2, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
-            else k_mp_dma<1, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            if (h->variant == 4) k_mp_dma<2, true, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 5) k_mp_dma<2, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 6) k_mp_dma<2, true, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->K == 2) k_mp_dma<2, false, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else k_mp_dma<1, false, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
         }
         return;
     }
@@ -1542,7 +1616,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
         d.ntile = ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3, 4: one block per K tiles
+        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3-6: one block per K tiles
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -1569,6 +1643,13 @@ lbmp_status upload(lbmp_mp* h) { return h->prec == LBMP_FP32 ? upload_geoms<floa
 bool dma_fits(const lbmp_mp* h) {
     for (const auto& g : h->g)
         if ((int64_t)16 * g.N + 4096 >= (int64_t)OOB || (int64_t)16 * g.NI + 4096 >= (int64_t)OOB) return false;
+    return true;
+}
+
+// Full-row LDS-DMA blocks (variants 5, 6) need every geometry one tile wide.
+bool full_rows(const lbmp_mp* h) {
+    for (const auto& g : h->g)
+        if (g.flow->nx != TX) return false;
     return true;
 }
 
@@ -1599,8 +1680,9 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || (v == 4 && K == 2)) && gs >= 1 && gs <= DMA_GMAX &&
-                         h->prec == LBMP_FP32 && dma_fits(h);
+        const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || (v == 4 && K == 2) ||
+                          ((v == 5 || v == 6) && K == 2 && full_rows(h))) &&
+                         gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
         if (nread == 3 && (ok01 || ok2 || ok3)) {
             h->variant = v;
             h->K = K;
@@ -1610,7 +1692,8 @@ lbmp_status autotune(lbmp_mp* h) {
         return fail(LBMP_EINVAL, "LBMP_TILE must be 'variant,K,species_per_block': variant 0|1 with K 1|2, "
                                  "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
                                  "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles), or variant 4 (FP32 only) with K = 2 "
-                                 "(z-planes per block); at most 64 species per block for 3 and 4");
+                                 "(z-planes per block), or variants 5, 6 (variants 3, 4 with full rows: FP32, nx = 64 in every "
+                                 "geometry) with K = 2; at most 64 species per block for 3-6");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1642,6 +1725,10 @@ lbmp_status autotune(lbmp_mp* h) {
             for (int K : {1, 2}) {
                 if (gs <= maxS || gs == 2) cand.push_back({K, gs, 3});
                 if (K == 2 && (gs <= maxS || gs == 2)) cand.push_back({K, gs, 4});
+                if (K == 2 && (gs <= maxS || gs == 2) && full_rows(h)) {
+                    cand.push_back({K, gs, 5});
+                    cand.push_back({K, gs, 6});
+                }
             }
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
