@@ -715,6 +715,8 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // of a tile are adjacent, so the blocks that read a plane as centre and as
 // z-neighbour, and the blocks that share a tile's link data, are resident
 // together. Waves without an interface node skip the sorption arithmetic.
+// Variants 5 and 6 are the 8-wave blocks of variants 3 and 4 on lattices one
+// tile wide (FR below).
 constexpr int RX = TX + 2;                       // haloed row
 // NH reduction tiles per block, stacked along y (ZX false: a TX x NH TY tile
 // of one plane) or along z (ZX true: a TX x TY tile of NH consecutive planes).
