@@ -171,12 +171,60 @@ def evaluate(sg, X: np.ndarray, Y: np.ndarray) -> dict:
     return out
 
 
-def query(lb, sg, mask: np.ndarray, peclet: float, k_a, k_d, times, velocity: np.ndarray | None = None):
+# Error-aware fallback: the held-out error of the network depends mostly on
+# the time (late times carry the dispersion, which the medium descriptors do
+# not fix) and on the Peclet number. Cells of half a decade in t by Pe band.
+T_EDGES = np.arange(0.0, 6.01, 0.5)
+PE_EDGES = np.array([0.0, 10.0, 30.0, 60.0, 100.0])
+
+
+def error_cells(X: np.ndarray) -> np.ndarray:
+    """Flat (log10 t, Pe) cell index of every feature row (edge cells absorb
+    values beyond the edges)."""
+    X = np.atleast_2d(X)
+    ti = np.clip(np.searchsorted(T_EDGES, X[:, 5], side="right") - 1, 0, len(T_EDGES) - 2)
+    pi = np.clip(np.searchsorted(PE_EDGES, X[:, 2], side="right") - 1, 0, len(PE_EDGES) - 2)
+    return ti * (len(PE_EDGES) - 1) + pi
+
+
+def error_table(X: np.ndarray, rel: np.ndarray, q: float = 95.0, min_rows: int = 50) -> np.ndarray:
+    """q-th percentile of the relative error of D per (log10 t, Pe) cell from
+    calibration rows; NaN (never trusted) where a cell has fewer than
+    `min_rows` rows."""
+    c = error_cells(X)
+    tab = np.full((len(T_EDGES) - 1) * (len(PE_EDGES) - 1), np.nan)
+    for k in np.unique(c):
+        m = c == k
+        if m.sum() >= min_rows:
+            tab[k] = np.percentile(rel[m], q)
+    return tab.reshape(len(T_EDGES) - 1, len(PE_EDGES) - 1)
+
+
+def trusted(X: np.ndarray, table: np.ndarray, tol: float) -> np.ndarray:
+    """Rows whose cell's calibrated error percentile is at most `tol`."""
+    v = np.asarray(table, dtype=np.float64).ravel()[error_cells(X)]
+    return ~np.isnan(v) & (v <= tol)
+
+
+def split_groups(X: np.ndarray, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Row masks of two halves of the (medium, Pe) groups of X (a group's rows
+    share porosity, specific surface and Pe), drawn at random."""
+    _, g = np.unique(np.atleast_2d(X)[:, :3], axis=0, return_inverse=True)
+    g = g.ravel()
+    perm = np.random.default_rng(seed).permutation(g.max() + 1)
+    first = np.isin(g, perm[: len(perm) // 2])
+    return first, ~first
+
+
+def query(lb, sg, mask: np.ndarray, peclet: float, k_a, k_d, times, velocity: np.ndarray | None = None,
+          table: np.ndarray | None = None, tol: float = 0.02):
     """D_x(t)/D_b for species (k_a[i], k_d[i]) in a medium at Peclet `peclet`.
 
     In-domain queries are answered by the network; if any feature lies outside
-    the training domain the plain method runs instead (flow from `velocity` if
-    given, otherwise the BGK solution rescaled to the Peclet number).
+    the training domain, or (with an error `table` from error_table) any
+    (t, Pe) cell's calibrated error exceeds `tol`, the plain method runs
+    instead (flow from `velocity` if given, otherwise the BGK solution
+    rescaled to the Peclet number).
     Returns (D/D_b array (n_species, n_times), "surrogate" | "method")."""
     import torch
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
@@ -190,7 +238,10 @@ def query(lb, sg, mask: np.ndarray, peclet: float, k_a, k_d, times, velocity: np
     fl.free()
     feats = np.array([[nf / mask.size, ni / mask.size, peclet, math.log10(a), math.log10(d), math.log10(t)]
                       for a, d in zip(k_a, k_d) for t in times])
-    if in_domain(feats).all() and (k_a > 0).all() and (times >= 1).all():
+    ok = in_domain(feats).all() and (k_a > 0).all() and (times >= 1).all()
+    if ok and table is not None:
+        ok = bool(trusted(feats, table, tol).all())
+    if ok:
         y = sg.predict(torch.tensor(feats, dtype=torch.float32, device="cuda"))
         sg.sync()
         return 10.0 ** y.cpu().numpy().reshape(len(k_a), len(times)), "surrogate"
@@ -306,12 +357,28 @@ def main(argv=None):
         sg.predict(xt)
     sg.sync()
     net_s = (time.time() - ts) / reps
+    # error-aware fallback: calibrate the cell errors on half of the held-out
+    # groups, measure what the gate lets through on the other half
+    pred = sg.predict(torch.tensor(Xte, dtype=torch.float32, device="cuda"))
+    sg.sync()
+    rel = np.abs(10.0 ** (pred.cpu().numpy().astype(np.float64) - Yte) - 1.0)
+    cal, tst = split_groups(Xte, args.seed)
+    table = error_table(Xte[cal], rel[cal])
+    gated = {"calibration_rows": int(cal.sum()), "test_rows": int(tst.sum()), "p95_table": table.tolist(),
+             "t_edges": T_EDGES.tolist(), "pe_edges": PE_EDGES.tolist()}
+    for tol in (0.02, 0.03, 0.05, 0.10):
+        ok = trusted(Xte[tst], table, tol)
+        r = rel[tst][ok]
+        gated[f"tol_{tol:g}"] = {"answered": float(ok.mean()),
+                                 "p50": float(np.percentile(r, 50)) if len(r) else None,
+                                 "p95": float(np.percentile(r, 95)) if len(r) else None,
+                                 "within_tol": float(np.mean(r <= tol)) if len(r) else None}
     res = {"metric": "surrogate D(t) error vs speedup", "train_rows": int(len(Ytr)),
            "test_rows": int(len(Yte)), "train_groups": args.train_groups, "test_groups": args.test_groups,
            "rel_err_D": ev, "final_train_loss": losses[-1],
            "plain_s_per_query": plain_s / answered, "surrogate_s_per_query": net_s / len(Yte),
            "speedup": (plain_s / answered) / (net_s / len(Yte)),
-           "generation_s": t_gen, "training_s": t_train, "epochs": args.epochs}
+           "generation_s": t_gen, "training_s": t_train, "epochs": args.epochs, "gated": gated}
     print(json.dumps(res), flush=True)
     sg.free()
 

@@ -182,3 +182,31 @@ def test_dataset_rows_and_fallback(lb):
     assert how2 == "surrogate" and D2.shape == (2, 3) and np.isfinite(D2).all()
     mp.free()
     sg.free()
+
+
+def test_error_gated_fallback(lb):
+    """With an error table, an in-domain query goes to the network only where
+    every (t, Pe) cell's calibrated error is within the tolerance; otherwise
+    the method runs and equals a direct run."""
+    from paper_1303_2470_amd import inputs, surrogate
+    sg = lb.Surrogate(256, seed=1)
+    mask = inputs.sphere_pack(32, 4, 0.5, seed=3)
+    u = inputs.random_velocity(mask, 0.005, seed=4)
+    nt, npe = len(surrogate.T_EDGES) - 1, len(surrogate.PE_EDGES) - 1
+    table = np.full((nt, npe), 0.01)
+    table[2:, :] = 0.5                             # log10 t >= 1: not trusted at 5 %
+    D, how = surrogate.query(lb, sg, mask, 10.0, [0.01], [0.02], [1, 3], velocity=u, table=table, tol=0.05)
+    assert how == "surrogate" and D.shape == (1, 2)
+    D, how = surrogate.query(lb, sg, mask, 10.0, [0.01], [0.02], [1, 30], velocity=u, table=table, tol=0.05)
+    assert how == "method"
+    fl = lb.lb_flow_from_velocity(mask, u)
+    mp = lb.mp_init(fl, {"D_b": surrogate.D_B, "k_a": [0.01], "k_d": [0.02]}, 32, 30)
+    lb.mp_step_n(mp, 30)
+    ref = lb.mp_vacf(mp, 0)["D"][0, 0, [1, 30]] / surrogate.D_B
+    assert np.allclose(D[0], ref, rtol=1e-6)
+    table[:] = np.nan                              # no calibration: nothing is trusted
+    _, how = surrogate.query(lb, sg, mask, 10.0, [0.01], [0.02], [1], velocity=u, table=table, tol=1.0)
+    assert how == "method"
+    mp.free()
+    fl.free()
+    sg.free()
