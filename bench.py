@@ -153,13 +153,24 @@ def cpu_baseline(inputs, steps: int):
     col = oracle.bgk(inputs.slit_mask(1, 1, W + 2), 1.0, [g, 0, 0], 1e-10, 400000)
     u = np.broadcast_to(col["u"], (3, W + 2, NXY, NXY)).copy()
     t0 = time.time()
-    oracle.vacf(mask, u, 12 * D_B, float(ka[0]), float(kd[0]), steps)
+    ref = oracle.vacf(mask, u, 12 * D_B, float(ka[0]), float(kd[0]), steps)
     el = time.time() - t0
     nf = NXY * NXY * W
     return {"value": nf * steps / el, "unit": "fluid-node-species updates/s",
             "cores": oracle.threads(), "kind": "oracle",
             "sample": f"64x64x{W + 2} slit (widest of the workload), 1 species, {steps} steps, "
-                      f"FP64 stay form incl. its per-run set-up; {el:.1f}s"}
+                      f"FP64 stay form incl. its per-run set-up; {el:.1f}s",
+            "_D": oracle.d_of_t(ref["Z"], ref["V"])}
+
+
+def d_error_vs_oracle(D_gpu: np.ndarray, D_ref: np.ndarray) -> dict:
+    """Largest relative D(t) error over every recorded time and direction,
+    |D - D_ref| / max(|D_ref|, 1e-2 D_b) (FP32 storage resolves D to about
+    2^-24 Z(0)), against the 1e-5 tolerance."""
+    err = np.abs(D_gpu - D_ref) / np.maximum(np.abs(D_ref), 1e-2 * D_B)
+    return {"max_rel": float(err.max()), "tolerance": 1e-5, "times": int(D_ref.shape[-1]),
+            "directions": int(D_ref.shape[0]),
+            "case": "species 0 of the widest slit (W=64), t = 0 .. the oracle leg's steps, x/y/z"}
 
 
 def sequential_compare(lb, flows, species, steps: int, warmup: int) -> dict:
@@ -328,6 +339,10 @@ def main():
     # accuracy and invariants of this run
     out = lbmp.mp_vacf(mp, len(flows) - 1, total, 1)
     mass_err = float(np.abs(out["mass"].sum(axis=1) - 1).max())
+    D_first = None
+    if not args.no_cpu_baseline and args.workload == "slits":
+        n_t = min(args.cpu_steps, total) + 1   # D(t) of the widest slit's species 0, kept for the oracle check
+        D_first = lbmp.mp_vacf(mp, len(flows) - 1, 0, n_t)["D"][0]
     res = {
         "metric": "moment-prop node-species updates/s",
         "value": value,
@@ -357,7 +372,12 @@ def main():
     }
     mp.free()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps)
+        cb = cpu_baseline(inputs, args.cpu_steps)
+        D_ref = cb.pop("_D")
+        res["cpu_baseline"] = cb
+        if D_first is not None:
+            n_t = min(D_first.shape[-1], D_ref.shape[-1])
+            res["d_error_vs_oracle"] = d_error_vs_oracle(D_first[:, :n_t], D_ref[:, :n_t])
     print(json.dumps(res), flush=True)
 
 
