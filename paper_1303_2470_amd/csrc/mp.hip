@@ -53,9 +53,13 @@ struct GeomDev {
     const double* sig;         // [N] sum_i p_i(r), exact (FP64)
     const T* src;              // [N]
     const T* a;                // [3][N]
-    T* X0;                     // [S][4][N]
-    T* X1;                     // [S][4][N]
+    T* X0;                     // [S][4][NC]
+    T* X1;                     // [S][4][NC]
     T* Xa;                     // [S][4][NI]
+    // compact field storage (haloed LDS-DMA blocks): fluid node n at fidx[n]
+    // (-1 on solid nodes), NC = fluid nodes; dense otherwise: fidx null, NC = N
+    const int32_t* fidx;
+    int64_t NC;
     const T* coef;             // [S][4]
     const T* prob;             // [S][2] = p_a, p_d
     const double* kc;          // [S][KC]: p_a, p_d, c_0..c_3 (coef), -V_0..-V_2, FP64
@@ -854,6 +858,8 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int x = x0 + lx, y = y0 + ly, z = z0 + zp;
     const bool inplane = x < nx && y < ny && z < nz;
     const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
+    const int NC = (int)G.NC;  // nodes per stored field (fluid nodes when compact)
+    const int32_t* const fidx = G.fidx;
     const int n = inplane ? z * plane + y * nx + x : 0;
     const bool act = inplane && G.cls[n] != 0;
     const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
@@ -867,7 +873,9 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int sl = act ? G.slot[n] : -1;
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
-    const int offn = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
+    // link data are dense (offd); fields compact or dense (offn)
+    const int offd = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
+    const int offn = act ? (fidx ? fidx[n] : n) * 4 : OOB;
     // this thread's share of the stencil region: element e = j * DBLK + tid,
     // or (FR) the 4 nodes from x = 4 (lane % 16) of row 4 g + lane / 16,
     // g = j NW + wave
@@ -888,18 +896,18 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
             const int e = j * DBLK + tid;
             const int hy = e / (SH::NPL * RX), pz = (e / RX) % SH::NPL, hx = e % RX;
             const int m = e < RREG ? modp(z0 - 1 + pz, nz) * plane + modp(y0 - 1 + hy, ny) * nx + modp(x0 - 1 + hx, nx) : 0;
-            voff[j] = (e < RREG && G.cls[m] != 0) ? m * 4 : OOB;
+            voff[j] = (e < RREG && G.cls[m] != 0) ? (fidx ? fidx[m] : m) * 4 : OOB;
         }
     }
     double pin[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offn);
+    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offd);
     const double sig = __builtin_bit_cast(
         double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, (int64_t)N * 8), act ? n * 8 : OOB, 0, 0));
-    const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offn);
+    const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offd);
     float av[3];
 #pragma unroll
-    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offn);
+    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offd);
     // per-node VACF weights without a branch on the node's class
     const double actd = act ? 1.0 : 0.0;
     double avd[3];
@@ -920,8 +928,8 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     // voffset + soffset + immediate: a masked offset (OOB) stays beyond the
     // range and OOB + 3 fields + 4 KB does not wrap (the host keeps 16 N + 4 KB
     // and 16 N_I + 4 KB below OOB for this kernel).
-    const int NB = N * 4, NIB = NI * 4;
-    const int64_t sN = 4 * (int64_t)N, sNI = 4 * (int64_t)NI;
+    const int NB = NC * 4, NIB = NI * 4;  // bytes per stored field
+    const int64_t sN = 4 * (int64_t)NC, sNI = 4 * (int64_t)NI;
     // The immediate offset of an LDS-DMA load moves both the memory address and
     // the LDS destination, so copies whose destinations lie within 4 KB share
     // one LDS base (M0): copy j (and the adsorbed values, as copy RLD) goes to
@@ -1330,16 +1338,19 @@ template <typename T>
 __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __restrict__ ilist,
                              int64_t N, int64_t NI, int S, const double* __restrict__ spc,
                              const double* __restrict__ b64, const double* __restrict__ src64,
-                             T* __restrict__ X, T* __restrict__ Xa) {
-    // spc per species: rho_ref, Gamma_ref, V0, V1, V2
+                             const int32_t* __restrict__ fidx, int64_t NC, T* __restrict__ X,
+                             T* __restrict__ Xa) {
+    // spc per species: rho_ref, Gamma_ref, V0, V1, V2; fields dense (fidx
+    // null, NC = N) or compact (node n at fidx[n], solid nodes not stored)
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     const double rr = spc[5 * s], gr = spc[5 * s + 1];
-    if (n < N) {
+    if (n < N && (!fidx || fidx[n] >= 0)) {
         const bool fl = cls[n] != 0;
-        X[(int64_t)(4 * s) * N + n] = fl ? (T)(rr * src64[n]) : T(0);
+        const int64_t i = fidx ? fidx[n] : n;
+        X[(int64_t)(4 * s) * NC + i] = fl ? (T)(rr * src64[n]) : T(0);
         for (int q = 1; q < 4; ++q)
-            X[(int64_t)(4 * s + q) * N + n] = fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q]) : T(0);
+            X[(int64_t)(4 * s + q) * NC + i] = fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q]) : T(0);
     }
     if (n < NI) {
         Xa[(int64_t)(4 * s) * NI + n] = T(0);
@@ -1350,10 +1361,12 @@ __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __re
 // Uptake start: density 1/N_F on every fluid node (the first-moment fields of
 // each species stay zero).
 template <typename T>
-__global__ void k_init_uptake(const int8_t* __restrict__ cls, int64_t N, double rho0, T* __restrict__ X) {
+__global__ void k_init_uptake(const int8_t* __restrict__ cls, int64_t N, double rho0,
+                              const int32_t* __restrict__ fidx, int64_t NC, T* __restrict__ X) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (n < N) X[(int64_t)(4 * s) * N + n] = cls[n] != 0 ? (T)rho0 : T(0);
+    if (n < N && (!fidx || fidx[n] >= 0))
+        X[(int64_t)(4 * s) * NC + (fidx ? fidx[n] : n)] = cls[n] != 0 ? (T)rho0 : T(0);
 }
 
 // Time series of Z_g and D_g (discrete Eq. 3 about the mean drift) for one
@@ -1409,6 +1422,7 @@ struct GeomHost {
     // device buffers
     void *pin, *sig, *src, *a, *X0, *X1, *Xa, *coef, *prob;
     double *part, *series, *spc, *spc0, *kc, *zout, *dout;
+    int32_t* fidx;  // [N] index of a fluid node among the fluid nodes in lattice order, -1 on solid
 };
 
 }  // namespace lbmp
@@ -1463,6 +1477,7 @@ void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
     g.X0 = c.take<T>(S * 4 * N);
     g.X1 = c.take<T>(S * 4 * N);
     g.Xa = c.take<T>(S * 4 * NIa);
+    g.fidx = c.take<int32_t>(N);
     g.coef = c.take<T>(S * 4);
     g.prob = c.take<T>(S * 2);
     g.part = c.take<double>(S * g.ntile_max * NRED);
@@ -1602,6 +1617,13 @@ void do_steps(lbmp_mp* h, int64_t n, hipStream_t s) {
     }
 }
 
+// The haloed LDS-DMA blocks store the fields of fluid nodes only (a porous
+// medium's solid nodes would otherwise share cache lines with its fluid ones
+// and be fetched and written back with them); the other variants, and the
+// full-row blocks, whose 16-byte copies take 4 consecutive nodes, keep the
+// dense layout.
+bool compact_fields(const lbmp_mp* h) { return h->variant == 3 || h->variant == 4; }
+
 // Fill the device geometry table for the current (K, gsz).
 template <typename T>
 lbmp_status upload_geoms(lbmp_mp* h) {
@@ -1622,6 +1644,8 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
+        d.fidx = compact_fields(h) ? g.fidx : nullptr;
+        d.NC = compact_fields(h) ? g.nf : g.N;
         d.coef = (const T*)g.coef; d.prob = (const T*)g.prob;
         d.kc = g.kc;
         d.part = g.part; d.series = g.series;
@@ -1850,6 +1874,22 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     return LBMP_OK;
 }
 
+// Index of every fluid node among the fluid nodes in lattice order (-1 on
+// solid nodes), the address of its fields in compact storage.
+lbmp_status build_fidx(GeomHost& g, hipStream_t s) {
+    std::vector<int8_t> cls(g.N);
+    LBMP_HIP(hipMemcpyAsync(cls.data(), g.flow->d.cls, g.N, hipMemcpyDeviceToHost, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> fi(g.N);
+    int64_t c = 0;
+    for (int64_t n = 0; n < g.N; ++n) fi[n] = cls[n] ? (int32_t)c++ : -1;
+    if (c != g.nf) return fail(LBMP_ESTATE, "fluid node count %lld differs from the flow's %lld", (long long)c,
+                               (long long)g.nf);
+    LBMP_HIP(hipMemcpyAsync(g.fidx, fi.data(), g.N * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    return LBMP_OK;
+}
+
 // The state at t = 1 lives in the odd buffer X1; X0 starts at zero. In uptake
 // mode X1 holds the start tau = 0: density 1/N_F on every fluid node, first
 // moments and adsorbed densities zero.
@@ -1863,12 +1903,15 @@ lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
         LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * N * sizeof(T), s));
         LBMP_HIP(hipMemsetAsync(g.Xa, 0, (size_t)g.S * 4 * std::max<int64_t>(g.NI, 1) * sizeof(T), s));
         dim3 grid((unsigned)((N + BLK - 1) / BLK), (unsigned)g.S);
-        k_init_uptake<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, N, 1.0 / (double)g.nf, (T*)g.X1);
+        k_init_uptake<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, N, 1.0 / (double)g.nf,
+                                              compact_fields(h) ? g.fidx : nullptr,
+                                              compact_fields(h) ? g.nf : N, (T*)g.X1);
         LBMP_HIP(hipGetLastError());
         return LBMP_OK;
     }
     dim3 grid((unsigned)((std::max<int64_t>(N, g.NI) + BLK - 1) / BLK), (unsigned)g.S);
     k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64,
+                                         compact_fields(h) ? g.fidx : nullptr, compact_fields(h) ? g.nf : N,
                                          (T*)g.X1, (T*)g.Xa);
     LBMP_HIP(hipGetLastError());
     return LBMP_OK;
@@ -1881,6 +1924,8 @@ lbmp_status setup_all(lbmp_mp* h, hipStream_t s) {
         lbmp_status st = build_links<T>(h, g, s, r);
         if (st != LBMP_OK) return st;
         st = species_constants<T>(h, g, r, s);
+        if (st != LBMP_OK) return st;
+        st = build_fidx(g, s);
         if (st != LBMP_OK) return st;
         LBMP_HIP(hipMemsetAsync(g.X0, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
         LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
@@ -2135,9 +2180,11 @@ extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, do
     const int64_t N = g.N, NI = g.NI, NIa = std::max<int64_t>(NI, 1);
     const int64_t t = h->steps + 1;
     const size_t es = h->prec == LBMP_FP32 ? 4 : 8;
-    const char* base = static_cast<const char*>((t & 1) ? g.X1 : g.X0) + (size_t)species * 4 * N * es;
+    // fields of fluid nodes only (in lattice order) with the haloed LDS-DMA blocks
+    const int64_t NC = compact_fields(h) ? g.nf : N;
+    const char* base = static_cast<const char*>((t & 1) ? g.X1 : g.X0) + (size_t)species * 4 * NC * es;
     const char* abase = static_cast<const char*>(g.Xa) + (size_t)species * 4 * NIa * es;
-    std::vector<char> hx(4 * N * es), ha(4 * NIa * es);
+    std::vector<char> hx(4 * NC * es), ha(4 * NIa * es);
     std::vector<int8_t> cls(N);
     std::vector<int32_t> ilist(NIa);
     LBMP_HIP(hipMemcpyAsync(hx.data(), base, hx.size(), hipMemcpyDeviceToHost, h->stream));
@@ -2152,8 +2199,11 @@ extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, do
     const double rr = g.rho_ref[species], gr = g.gam_ref[species];
     for (int q = 0; q < 4; ++q) {
         const double cq = q == 0 ? 1.0 : g.V[3 * species + q - 1];
-        for (int64_t n = 0; n < N; ++n)
-            if (X) X[q * N + n] = cls[n] ? at(hx, q * N + n) + cq * rr : 0.0;
+        int64_t i = 0;  // index among the fluid nodes
+        for (int64_t n = 0; n < N; ++n) {
+            if (X) X[q * N + n] = cls[n] ? at(hx, q * NC + (NC == N ? n : i)) + cq * rr : 0.0;
+            if (cls[n]) ++i;
+        }
         if (Xads) {
             for (int64_t n = 0; n < N; ++n) Xads[q * N + n] = 0.0;
             for (int64_t i = 0; i < NI; ++i) Xads[q * N + ilist[i]] = at(ha, q * NIa + i) + cq * gr;
