@@ -56,8 +56,10 @@ struct GeomDev {
     T* X0;                     // [S][4][NC]
     T* X1;                     // [S][4][NC]
     T* Xa;                     // [S][4][NI]
-    // compact field storage (haloed LDS-DMA blocks): fluid node n at fidx[n]
-    // (-1 on solid nodes), NC = fluid nodes; dense otherwise: fidx null, NC = N
+    // compact storage (haloed LDS-DMA blocks): the fields and the link data
+    // (pin, sig, src, a: each row's first NC entries) of fluid node n at
+    // fidx[n] (-1 on solid nodes), NC = fluid nodes; dense otherwise: fidx
+    // null, NC = N
     const int32_t* fidx;
     int64_t NC;
     const T* coef;             // [S][4]
@@ -715,10 +717,10 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // fields ahead of the field being updated, through four LDS stages (stage =
 // quantity q). Nothing passes
 // through registers on its way in, so the tile's link data stay in registers
-// for all the fields of the block. Tiles run z-fastest and the species groups
-// of a tile are adjacent, so the blocks that read a plane as centre and as
-// z-neighbour, and the blocks that share a tile's link data, are resident
-// together. Waves without an interface node skip the sorption arithmetic.
+// for all the fields of the block. Tiles run z-fastest within bands of a few
+// tiles along y and the species groups of a tile are adjacent, so the blocks
+// that read a plane or a row as centre and as neighbour, and the blocks that
+// share a tile's link data, are resident together. Waves without an interface node skip the sorption arithmetic.
 // Variants 5 and 6 are the 8-wave blocks of variants 3 and 4 on lattices one
 // tile wide (FR below).
 constexpr int RX = TX + 2;                       // haloed row
@@ -845,11 +847,18 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int grp = (int)(local % G.ngrp);
     const int64_t btile = local / G.ngrp;  // block tile; reduction tiles NH btile + half
     const int nx = G.nx, ny = G.ny, nz = G.nz;
-    const int ntx = (nx + TX - 1) / TX;
+    // Block tiles in bands of YB tiles along y: x tile, then band, then z,
+    // then y within the band (the last band may be narrower), so that the
+    // blocks resident on one XCD at a time cover a few tiles in y by many in
+    // z and share halo rows as well as halo planes in its L2.
     const int nzb = ZX ? (nz + NH - 1) / NH : nz;  // block positions along z
-    const int z0 = (int)(btile % nzb) * (ZX ? NH : 1);
-    const int64_t cxy = btile / nzb;
-    const int x0 = (int)(cxy % ntx) * TX, y0 = (int)(cxy / ntx) * DTY;
+    const int nyt = (ny + DTY - 1) / DTY;           // block positions along y
+    const int64_t per_x = (int64_t)nyt * nzb;
+    const int xt = (int)(btile / per_x), rb = (int)(btile % per_x);
+    constexpr int YB = 4;
+    const int band = rb / (YB * nzb), bs = min(YB, nyt - band * YB), rr = rb - band * YB * nzb;
+    const int z0 = (rr / bs) * (ZX ? NH : 1);
+    const int x0 = xt * TX, y0 = (band * YB + rr % bs) * DTY;
     const int tid = threadIdx.x, lx = tid % TX;
     const int ly = ZX ? (tid / TX) % TY : tid / TX, zp = ZX ? tid / BLK : 0;  // row, plane in the block
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -873,8 +882,9 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int sl = act ? G.slot[n] : -1;
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
-    // link data are dense (offd); fields compact or dense (offn)
-    const int offd = act ? n * 4 : OOB, offa = isI ? sl * 4 : OOB;
+    // fields and link data of node n at offn: its index among the fluid
+    // nodes (compact storage) or n
+    const int offa = isI ? sl * 4 : OOB;
     const int offn = act ? (fidx ? fidx[n] : n) * 4 : OOB;
     // this thread's share of the stencil region: element e = j * DBLK + tid,
     // or (FR) the 4 nodes from x = 4 (lane % 16) of row 4 g + lane / 16,
@@ -901,13 +911,13 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     }
     double pin[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offd);
+    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offn);
     const double sig = __builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, (int64_t)N * 8), act ? n * 8 : OOB, 0, 0));
-    const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offd);
+        double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, (int64_t)N * 8), act ? offn * 2 : OOB, 0, 0));
+    const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offn);
     float av[3];
 #pragma unroll
-    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offd);
+    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * N, (int64_t)N * 4), offn);
     // per-node VACF weights without a branch on the node's class
     const double actd = act ? 1.0 : 0.0;
     double avd[3];
@@ -1874,6 +1884,37 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     return LBMP_OK;
 }
 
+// rows x N values (row stride N) -> the fluid nodes' values at the head of
+// each row, in lattice order
+template <typename V>
+__global__ void k_gather_fluid(const int32_t* __restrict__ fidx, int64_t N, const V* __restrict__ in,
+                               V* __restrict__ out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.y;
+    if (n < N && fidx[n] >= 0) out[r * N + fidx[n]] = in[r * N + n];
+}
+
+// Link tables of geometry g in compact storage, through the set-up scratch
+// (free once the state is initialised).
+template <typename T>
+lbmp_status compact_links(lbmp_mp* h, GeomHost& g, hipStream_t s) {
+    const int64_t N = g.N;
+    auto one = [&](void* buf, int rows, size_t es, auto tag) -> lbmp_status {
+        using V = decltype(tag);
+        V* tmp = reinterpret_cast<V*>(h->setup_tmp);
+        dim3 grid((unsigned)((N + BLK - 1) / BLK), (unsigned)rows);
+        k_gather_fluid<V><<<grid, BLK, 0, s>>>(g.fidx, N, static_cast<const V*>(buf), tmp);
+        LBMP_HIP(hipGetLastError());
+        LBMP_HIP(hipMemcpyAsync(buf, tmp, (size_t)rows * N * es, hipMemcpyDeviceToDevice, s));
+        return LBMP_OK;
+    };
+    lbmp_status st = one(g.pin, NL, sizeof(T), T());
+    if (st == LBMP_OK) st = one(g.sig, 1, sizeof(double), double());
+    if (st == LBMP_OK) st = one(g.src, 1, sizeof(T), T());
+    if (st == LBMP_OK) st = one(g.a, 3, sizeof(T), T());
+    return st;
+}
+
 // Index of every fluid node among the fluid nodes in lattice order (-1 on
 // solid nodes), the address of its fields in compact storage.
 lbmp_status build_fidx(GeomHost& g, hipStream_t s) {
@@ -1950,6 +1991,10 @@ lbmp_status setup_all(lbmp_mp* h, hipStream_t s) {
         if (st != LBMP_OK) return st;
         st = init_state<T>(h, g, s);
         if (st != LBMP_OK) return st;
+        if (compact_fields(h)) {
+            st = compact_links<T>(h, g, s);
+            if (st != LBMP_OK) return st;
+        }
     }
     LBMP_HIP(hipStreamSynchronize(s));
     return LBMP_OK;
