@@ -74,17 +74,17 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(open(os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip"), "rb").read()).hexdigest()
 
 
-def traffic_record(tile: str):
+def traffic_record(key: str):
     """Measured HBM bytes per launch of the propagation kernel, if taken on the
-    current kernel source with the same tile choice ("variant,K,species per
-    block") as this run (profiles/mp_step_traffic.json holds one entry per
-    measured tile)."""
+    current kernel source with the same workload and tile choice
+    ("workload:variant,K,species per block") as this run
+    (profiles/mp_step_traffic.json holds one entry per measured key)."""
     if not os.path.exists(TRAFFIC_PATH):
         return None
     rec = json.load(open(TRAFFIC_PATH))
     if rec.get("kernel_source_sha256") != kernel_source_sha():
         return None
-    ent = rec.get("tiles", {}).get(tile)
+    ent = rec.get("tiles", {}).get(key)
     return ent.get("bytes_per_launch") if ent else None
 
 
@@ -263,13 +263,14 @@ def main():
         print(json.dumps(rocprof_summary(args.rocprof_summary), indent=1))
         return
     if args.traffic_record:
-        # one entry per tile (LBMP_TILE of the counter runs); entries of an
+        # one entry per workload and tile (--workload, LBMP_TILE of the counter runs); entries of an
         # older kernel source are dropped
         ent = traffic_from_counters(args.traffic_record, 1024 << 20)
         rec = json.load(open(TRAFFIC_PATH)) if os.path.exists(TRAFFIC_PATH) else {}
         if rec.get("kernel_source_sha256") != kernel_source_sha():
             rec = {"kernel": "k_mp_dma", "kernel_source_sha256": kernel_source_sha(), "tiles": {}}
-        rec["tiles"][ent["tile"]] = ent
+        ent["workload"] = args.workload
+        rec["tiles"][f'{args.workload}:{ent["tile"]}'] = ent
         with open(TRAFFIC_PATH, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(ent))
@@ -335,7 +336,7 @@ def main():
     alg = sum(n_species * (32 * f + 32 * n) + 16 * f for f, n in zip(nf, ni))
     k_avg_s = k_ms / 1e3 / args.steps
     achieved = alg / k_avg_s / 1e9
-    traffic = traffic_record(f'{st["kernel_variant"]},{st["tile_k"]},{st["species_per_block"]}')
+    traffic = traffic_record(f'{args.workload}:{st["kernel_variant"]},{st["tile_k"]},{st["species_per_block"]}')
     # accuracy and invariants of this run
     out = lbmp.mp_vacf(mp, len(flows) - 1, total, 1)
     mass_err = float(np.abs(out["mass"].sum(axis=1) - 1).max())
