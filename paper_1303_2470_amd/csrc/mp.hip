@@ -70,8 +70,9 @@ struct GeomDev {
 };
 
 struct Ctl {
-    int64_t t;     // time of the current state (1 after init)
-    int64_t tmax;  // last recordable time
+    int64_t t;      // time of the current state (1 after init)
+    int64_t tmax;   // last recordable time
+    uint32_t done;  // blocks of the series reduction finished in this step (0 between steps)
 };
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -1180,7 +1181,8 @@ __global__ void __launch_bounds__(BLK) k_mp_reduce_chunks(const GeomDev<T>* __re
     const int gi = work[2 * w], s = work[2 * w + 1];
     const GeomDev<T>& G = geoms[gi];
     const int64_t ntile = G.ntile;
-    const double* P = G.part + (int64_t)s * ntile * NRED;
+    using gdp = const __attribute__((address_space(1))) double*;  // global loads, not flat
+    const gdp P = (gdp)(G.part + (int64_t)s * ntile * NRED);
     const int64_t i0 = (int64_t)c * RCH, i1 = min(ntile, i0 + RCH);
     double acc[NRED];
 #pragma unroll
@@ -1194,42 +1196,72 @@ __global__ void __launch_bounds__(BLK) k_mp_reduce_chunks(const GeomDev<T>* __re
 }
 
 // Sum the block partials (or, with nch > 0, the chunk sums) of every
-// (geometry, species) into the series at the current time, in a fixed order.
+// (geometry, species) into the series at the current time, in a fixed order,
+// one block of RED_T threads per pair, then advance the time: the partials of
+// a pair are read as one flat array (thread i adds entries i, i + RED_T, ...,
+// all of sum i % NRED, in turn into eight accumulators), the 32 threads of
+// each sum are added by a fixed tree, and the last block to finish moves the
+// state time on (every block has read it by then).
+constexpr int RED_T = 256;
+
 template <typename T>
-__global__ void k_mp_reduce(const GeomDev<T>* __restrict__ geoms, int ngeom,
-                            const int32_t* __restrict__ work, int nwork, int nch,
-                            const double* __restrict__ chunk, Ctl* __restrict__ ctl) {
-    const int w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
+__global__ void __launch_bounds__(RED_T) k_mp_reduce(const GeomDev<T>* __restrict__ geoms, int ngeom,
+                                                     const int32_t* __restrict__ work, int nwork, int nch,
+                                                     const double* __restrict__ chunk, Ctl* __restrict__ ctl) {
+    static_assert(RED_T % (64 * 1) == 0 && 64 % NRED == 0, "a thread's entries belong to one sum");
+    __shared__ double wsum[RED_T / 64][NRED];
+    __shared__ bool last;
+    const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t t = ctl->t;
-    if (w < nwork) {
-        const int gi = work[2 * w], s = work[2 * w + 1];
-        const GeomDev<T>& G = geoms[gi];
-        const int64_t ntile = nch > 0 ? nch : G.ntile;
-        const double* P = nch > 0 ? chunk + (int64_t)w * nch * NRED : G.part + (int64_t)s * G.ntile * NRED;
-        double acc[NRED];
+    const int gi = work[2 * w], s = work[2 * w + 1];
+    const GeomDev<T>& G = geoms[gi];
+    const int64_t ntile = nch > 0 ? nch : G.ntile;
+    // global address space: flat loads would also count as LDS traffic and
+    // serialise the loads below
+    using gdp = const __attribute__((address_space(1))) double*;
+    const gdp P = (gdp)(nch > 0 ? chunk + (int64_t)w * nch * NRED : G.part + (int64_t)s * G.ntile * NRED);
+    const int64_t len = ntile * NRED;
+    // eight loads in flight per thread, then their sums (eight accumulators)
+    double acc[8];
 #pragma unroll
-        for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-        for (int64_t i = lane; i < ntile; i += 64)
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    int64_t i = tid;
+    for (; i + 7 * RED_T < len; i += 8 * RED_T) {
+        double x[8];
 #pragma unroll
-            for (int k = 0; k < NRED; ++k) acc[k] += P[i * NRED + k];
+        for (int u = 0; u < 8; ++u) x[u] = P[i + u * RED_T];
 #pragma unroll
-        for (int k = 0; k < NRED; ++k)
+        for (int u = 0; u < 8; ++u) acc[u] += x[u];
+    }
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-        if (lane < NRED && t <= ctl->tmax) {
-            double v = acc[0];
+    for (int u = 0; u < 7; ++u)
+        if (i + u * RED_T < len) acc[u] += P[i + u * RED_T];
+    double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    // lanes l, l ^ 8, l ^ 16, ... hold the same sum (l % 8)
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < NRED) wsum[wv][lane] = v;
+    __syncthreads();
+    if (tid < NRED && t <= ctl->tmax) {
+        double r = wsum[0][tid];
 #pragma unroll
-            for (int k = 1; k < NRED; ++k)
-                if (lane == k) v = acc[k];
-            G.series[((t - 1) * G.S + s) * NRED + lane] = v;
-        }
+        for (int k = 1; k < RED_T / 64; ++k) r += wsum[k][tid];
+        G.series[((t - 1) * G.S + s) * NRED + tid] = r;
+    }
+    // time advance by the last block
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->done, 1u) == (unsigned)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && tid == 0) {
+        ctl->done = 0;
+        ctl->t = t + 1;
     }
 }
 
-__global__ void k_advance(Ctl* ctl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t += 1;
-}
 
 // ------------------------------------------------------------------ set-up
 // Link probabilities of Eq. 8 (local equilibrium, Q = 1), FP64, per node and
@@ -1610,9 +1642,8 @@ void launch_step_tail(lbmp_mp* h, hipStream_t s) {
     auto* G = static_cast<const GeomDev<T>*>(h->geoms_dev);
     if (h->nch > 1)
         k_mp_reduce_chunks<T><<<(unsigned)(h->nwork * h->nch), BLK, 0, s>>>(G, h->work, h->nch, h->chunk);
-    k_mp_reduce<T><<<(unsigned)((h->nwork + 3) / 4), 256, 0, s>>>(G, h->ngeom, h->work, h->nwork,
-                                                                  h->nch > 1 ? h->nch : 0, h->chunk, h->ctl);
-    k_advance<<<1, 64, 0, s>>>(h->ctl);
+    k_mp_reduce<T><<<(unsigned)h->nwork, RED_T, 0, s>>>(G, h->ngeom, h->work, h->nwork, h->nch > 1 ? h->nch : 0,
+                                                         h->chunk, h->ctl);
 }
 
 template <typename T>
