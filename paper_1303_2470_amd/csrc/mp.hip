@@ -718,10 +718,11 @@ __global__ void __launch_bounds__(BLK) k_mp_march(const GeomDev<T>* __restrict__
 // fields ahead of the field being updated, through four LDS stages (stage =
 // quantity q). Nothing passes
 // through registers on its way in, so the tile's link data stay in registers
-// for all the fields of the block. Tiles run z-fastest within bands of a few
-// tiles along y and the species groups of a tile are adjacent, so the blocks
-// that read a plane or a row as centre and as neighbour, and the blocks that
-// share a tile's link data, are resident together. Waves without an interface node skip the sorption arithmetic.
+// for all the fields of the block. Tiles run x-fastest, then along y within
+// bands of a few tiles, then along z, and the species groups of a tile are
+// adjacent, so the blocks that read a plane, a row or a column as centre and
+// as neighbour, and the blocks that share a tile's link data, are resident
+// together. Waves without an interface node skip the sorption arithmetic.
 // Variants 5 and 6 are the 8-wave blocks of variants 3 and 4 on lattices one
 // tile wide (FR below).
 constexpr int RX = TX + 2;                       // haloed row
@@ -848,18 +849,21 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int grp = (int)(local % G.ngrp);
     const int64_t btile = local / G.ngrp;  // block tile; reduction tiles NH btile + half
     const int nx = G.nx, ny = G.ny, nz = G.nz;
-    // Block tiles in bands of YB tiles along y: x tile, then band, then z,
-    // then y within the band (the last band may be narrower), so that the
-    // blocks resident on one XCD at a time cover a few tiles in y by many in
-    // z and share halo rows as well as halo planes in its L2.
+    // Block tiles in bands of YB tiles along y: band, then z, then y within
+    // the band (the last band may be narrower), then x, so that the blocks
+    // resident on one XCD at a time cover whole rows, a few tiles in y and
+    // several in z, and share halo columns, rows and planes (and the cache
+    // lines that a row's tiles split) in its L2.
     const int nzb = ZX ? (nz + NH - 1) / NH : nz;  // block positions along z
     const int nyt = (ny + DTY - 1) / DTY;           // block positions along y
-    const int64_t per_x = (int64_t)nyt * nzb;
-    const int xt = (int)(btile / per_x), rb = (int)(btile % per_x);
+    const int ntx = (nx + TX - 1) / TX;             // block positions along x
     constexpr int YB = 4;
-    const int band = rb / (YB * nzb), bs = min(YB, nyt - band * YB), rr = rb - band * YB * nzb;
-    const int z0 = (rr / bs) * (ZX ? NH : 1);
-    const int x0 = xt * TX, y0 = (band * YB + rr % bs) * DTY;
+    const int64_t per_band = (int64_t)YB * nzb * ntx;
+    const int band = (int)(btile / per_band), bs = min(YB, nyt - band * YB);
+    const int rr = (int)(btile - band * per_band);
+    const int xt = rr % ntx, r2 = rr / ntx;
+    const int z0 = (r2 / bs) * (ZX ? NH : 1);
+    const int x0 = xt * TX, y0 = (band * YB + r2 % bs) * DTY;
     const int tid = threadIdx.x, lx = tid % TX;
     const int ly = ZX ? (tid / TX) % TY : tid / TX, zp = ZX ? tid / BLK : 0;  // row, plane in the block
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
