@@ -755,6 +755,8 @@ struct DmaShape {
     // wait for it: the copies of the next two fields and the stores of the
     // two before (with and without interface nodes in the wave)
     static constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2;
+    // waves without a node to update (lane compaction) copy and store nothing else
+    static constexpr int WAIT_IDLE = 2 * NCP;
 };
 constexpr int DMA_GMAX = 64;                     // species per block
 constexpr int NSUM = 5;                          // per-node block sums of a species
@@ -829,9 +831,14 @@ struct Stages {
     __device__ __forceinline__ float* at() const { return p[Q]; }
 };
 
-template <int NH, bool ZX, bool FR>
+// LC (lane compaction, haloed blocks only): the fluid nodes of the block are
+// handed to its first threads in thread order, so that waves left without a
+// node copy, synchronise and add block sums but skip the update arithmetic
+// (porous media, where most lanes of a tile sit on solid nodes).
+template <int NH, bool ZX, bool FR, bool LC = false>
 __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_dma(const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz,
                                                int64_t nblocks, const Ctl* __restrict__ ctl) {
+    static_assert(!(LC && FR), "lane compaction needs the haloed region (a wave is not a row)");
     using SH = DmaShape<NH, ZX, FR>;
     constexpr int DTY = SH::DTY, DBLK = SH::DBLK, RREG = SH::RREG, RLD = SH::RLD, STAGE = SH::STAGE;
     constexpr int NCP = SH::NCP, REGION = SH::REGION;
@@ -864,26 +871,57 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const int xt = rr % ntx, r2 = rr / ntx;
     const int z0 = (r2 / bs) * (ZX ? NH : 1);
     const int x0 = xt * TX, y0 = (band * YB + r2 % bs) * DTY;
-    const int tid = threadIdx.x, lx = tid % TX;
-    const int ly = ZX ? (tid / TX) % TY : tid / TX, zp = ZX ? tid / BLK : 0;  // row, plane in the block
+    const int tid = threadIdx.x;
+    // block position of thread t: x, row, plane
+    auto pos_x = [](int t) { return t % TX; };
+    auto pos_y = [](int t) { return ZX ? (t / TX) % TY : t / TX; };
+    auto pos_z = [](int t) { return ZX ? t / BLK : 0; };
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
     const int hf = wv >> 2, w4 = wv & 3;        // half of the block, wave within it
     const int64_t tile = NH * btile + hf;       // this wave's reduction tile
-    const int x = x0 + lx, y = y0 + ly, z = z0 + zp;
-    const bool inplane = x < nx && y < ny && z < nz;
     const int N = (int)G.N, NI = (int)G.NI, plane = nx * ny, S = G.S;
     const int NC = (int)G.NC;  // nodes per stored field (fluid nodes when compact)
     const int32_t* const fidx = G.fidx;
-    const int n = inplane ? z * plane + y * nx + x : 0;
-    const bool act = inplane && G.cls[n] != 0;
     const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
     const int64_t ntile = G.ntile;
     double* const part = G.part;
-    if (!__syncthreads_or(act)) {  // a tile without fluid: zero sums of every half
+    // the thread's own node
+    const int ox = x0 + pos_x(tid), oy = y0 + pos_y(tid), oz = z0 + pos_z(tid);
+    const bool oin = ox < nx && oy < ny && oz < nz;
+    const bool oact = oin && G.cls[oin ? oz * plane + oy * nx + ox : 0] != 0;
+    if (!__syncthreads_or(oact)) {  // a tile without fluid: zero sums of every half
         for (int i = tid; i < NH * NRED * (s1 - s0); i += DBLK)
             part[((int64_t)(s0 + i / (NH * NRED)) * ntile + NH * btile + (i / NRED) % NH) * NRED + i % NRED] = 0.0;
         return;
     }
+    // the node this thread updates: its own, or with LC the tid-th fluid node
+    // of the block in thread order (none past the block's fluid count)
+    __shared__ int lc_cnt[LC ? SH::NW : 1];
+    __shared__ unsigned short lc_node[LC ? DBLK : 1];
+    int at_t = tid;
+    bool lc_has = true, idle = false;  // idle: wave-uniform, no node in the wave
+    if constexpr (LC) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(oact);
+        if ((tid & 63) == 0) lc_cnt[wv] = (int)__builtin_popcountll(m);
+        __syncthreads();
+        int base = 0, F = 0;
+        for (int w = 0; w < SH::NW; ++w) {
+            const int c = lc_cnt[w];
+            base += w < wv ? c : 0;
+            F += c;
+        }
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (oact) lc_node[base + below] = (unsigned short)tid;
+        __syncthreads();
+        lc_has = tid < F;
+        at_t = lc_has ? (int)lc_node[tid] : 0;
+        idle = __builtin_amdgcn_readfirstlane(wv * 64 >= F ? 1 : 0) != 0;
+    }
+    const int lx = pos_x(at_t), ly = pos_y(at_t), zp = pos_z(at_t);  // updated node: x, row, plane in the block
+    const int x = x0 + lx, y = y0 + ly, z = z0 + zp;
+    const bool inplane = lc_has && x < nx && y < ny && z < nz;
+    const int n = inplane ? z * plane + y * nx + x : 0;
+    const bool act = inplane && G.cls[n] != 0;
     const int sl = act ? G.slot[n] : -1;
     const bool isI = sl >= 0;
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;  // wave-uniform
@@ -1039,8 +1077,10 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     // same barriers). firstc / lastc: the block's first / last species, whose
     // first / last two fields wait for every copy in flight (fewer operations
     // follow their copies than the steady-state wait counts assume).
-    auto run = [&](auto anyc) {
+    auto run = [&](auto anyc, auto idlec) {
         constexpr bool ANYI = decltype(anyc)::value;
+        constexpr bool IDLE = decltype(idlec)::value;  // no node in the wave: no update, no stores
+        static_assert(!(IDLE && ANYI), "an idle wave has no interface node");
         const float* in_s = Xin + (int64_t)s0 * sN;  // species s of the input fields
         const float* ina_s = Xa + (int64_t)s0 * sNI;
         float* out_s = Xout + (int64_t)s0 * sN;
@@ -1074,6 +1114,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 // f+1, f+2 and the stores of f-2, f-1 (2 (NCP + 1) + 2 * 2 with
                 // interface nodes in the wave, 2 NCP + 2 without)
                 if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
+                else if constexpr (IDLE) barrier_vm<SH::WAIT_IDLE>();
                 else if constexpr (ANYI) barrier_vm<SH::WAIT_I>();
                 else barrier_vm<SH::WAIT_N>();
                 if constexpr (q == 0) {
@@ -1085,58 +1126,60 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     pend2 = pend;
                     pend = -1;
                 }
-                // one live base offset: addresses derived from it are not
-                // hoisted out of the loop (each would hold a register for the
-                // whole loop)
-                int cbb = 4 * cb;
-                asm volatile("" : "+v"(cbb));
-                // volatile: one ds_read_b32 per value, its stencil offset in the
-                // instruction's immediate (merged pairs need a base register each)
-                using lvf = const volatile __attribute__((address_space(3))) float;
-                lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
-                // all 19 values first (the node's own first: the chain starts
-                // with it), then the arithmetic; v[k] is the value at r - c_k
-                float v[NL], c0;
-                if constexpr (FR) {
-                    // a wave is one periodic row (lane = x): the values at x -+ 1
-                    // are the x-centred values of the same row in the lanes
-                    // beside it (a rotation of the wave by one lane)
-                    c0 = sb[SH::at(1, 1, 0)];
-#pragma unroll
-                    for (int k = 0; k < NL; ++k)
-                        if (lcx(k) == 0) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 0)];
-#pragma unroll
-                    for (int k = 0; k < NL; ++k)
-                        if (lcx(k) != 0) {
-                            const float b = row_link(k) < 0 ? c0 : v[row_link(k)];
-                            v[k] = lcx(k) > 0 ? dpp_f32<DPP_WAVE_ROR1>(b) : dpp_f32<DPP_WAVE_ROL1>(b);
-                        }
-                } else {
-                    c0 = sb[SH::at(1, 1, 1)];
-#pragma unroll
-                    for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                if constexpr (!IDLE) {  // an idle wave updates no node
+                    // one live base offset: addresses derived from it are not
+                    // hoisted out of the loop (each would hold a register for the
+                    // whole loop)
+                    int cbb = 4 * cb;
+                    asm volatile("" : "+v"(cbb));
+                    // volatile: one ds_read_b32 per value, its stencil offset in the
+                    // instruction's immediate (merged pairs need a base register each)
+                    using lvf = const volatile __attribute__((address_space(3))) float;
+                    lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
+                    // all 19 values first (the node's own first: the chain starts
+                    // with it), then the arithmetic; v[k] is the value at r - c_k
+                    float v[NL], c0;
+                    if constexpr (FR) {
+                        // a wave is one periodic row (lane = x): the values at x -+ 1
+                        // are the x-centred values of the same row in the lanes
+                        // beside it (a rotation of the wave by one lane)
+                        c0 = sb[SH::at(1, 1, 0)];
+    #pragma unroll
+                        for (int k = 0; k < NL; ++k)
+                            if (lcx(k) == 0) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 0)];
+    #pragma unroll
+                        for (int k = 0; k < NL; ++k)
+                            if (lcx(k) != 0) {
+                                const float b = row_link(k) < 0 ? c0 : v[row_link(k)];
+                                v[k] = lcx(k) > 0 ? dpp_f32<DPP_WAVE_ROR1>(b) : dpp_f32<DPP_WAVE_ROL1>(b);
+                            }
+                    } else {
+                        c0 = sb[SH::at(1, 1, 1)];
+    #pragma unroll
+                        for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
+                    }
+                    const double xc = (double)c0;
+                    double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
+                    acc0 = __builtin_fma(cq[q], src, acc0);
+    #pragma unroll
+                    for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
+                        if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
+                        else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
+                    }
+                    double nvx = acc0 + acc1;
+                    const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
+                    if constexpr (q == 0) red[3] += act ? xc : 0.0;
+                    else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
+                    if constexpr (ANYI) {  // sorption (Eqs. 9, 10) where the wave has interface nodes
+                        const double xa = (double)stg.at<q>()[REGION + tid];
+                        const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
+                        nvx = (nvx - fa) + fd;
+                        bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
+                        if constexpr (q == 0) red[4] += xa;
+                        else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
+                    }
+                    bstore(sround(nvx, r), rout, offn, q * NB);
                 }
-                const double xc = (double)c0;
-                double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
-                acc0 = __builtin_fma(cq[q], src, acc0);
-#pragma unroll
-                for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
-                    if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
-                    else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
-                }
-                double nvx = acc0 + acc1;
-                const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
-                if constexpr (q == 0) red[3] += act ? xc : 0.0;
-                else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
-                if constexpr (ANYI) {  // sorption (Eqs. 9, 10) where the wave has interface nodes
-                    const double xa = (double)stg.at<q>()[REGION + tid];
-                    const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
-                    nvx = (nvx - fa) + fd;
-                    bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
-                    if constexpr (q == 0) red[4] += xa;
-                    else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
-                }
-                bstore(sround(nvx, r), rout, offn, q * NB);
                 // field f + 3: quantity 3 of this species, or quantity q - 1 of the next
                 if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
                 else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
@@ -1161,8 +1204,9 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
             species(s1 - 1, F_(), T_());
         }
     };
-    if (anyI) run(T_());
-    else run(F_());
+    if (idle) run(F_(), T_());
+    else if (anyI) run(T_(), F_());
+    else run(F_(), F_());
     barrier_vm0();
     finish(pend2);
     barrier_vm0();
@@ -1486,7 +1530,7 @@ struct lbmp_mp {
     double* chunk;   // [nwork][nch_max][NRED] chunk sums of the series reduction
     int nch_max, nch;
     double* setup_tmp;
-    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3-6: LDS DMA (FP32)
+    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3-7: LDS DMA (FP32)
     int uptake;           // out-of-equilibrium density propagation (no VACF)
     int64_t nblocks;
     hipGraph_t graph = nullptr;
@@ -1504,8 +1548,8 @@ int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     // (variant 5: the same with full rows)
     if (variant == 3 || variant == 5)
         return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + K * TY - 1) / (K * TY)) * f->nz;
-    // variant 4 (6: full rows): K reduction tiles (TX x TY) per block of K planes
-    if (variant == 4 || variant == 6) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * ((f->nz + K - 1) / K);
+    // variant 4 (6: full rows, 7: lane compaction): K reduction tiles (TX x TY) per block of K planes
+    if (variant == 4 || variant == 6 || variant == 7) return K * (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * ((f->nz + K - 1) / K);
     if (variant >= 1) return (int64_t)((f->nx + TX - 1) / TX) * ((f->ny + TY - 1) / TY) * zb;
     return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
@@ -1617,6 +1661,7 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
             if (h->variant == 4) k_mp_dma<2, true, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 5) k_mp_dma<2, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 6) k_mp_dma<2, true, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 7) k_mp_dma<2, true, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->K == 2) k_mp_dma<2, false, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else k_mp_dma<1, false, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
         }
@@ -1667,7 +1712,7 @@ void do_steps(lbmp_mp* h, int64_t n, hipStream_t s) {
 // and be fetched and written back with them); the other variants, and the
 // full-row blocks, whose 16-byte copies take 4 consecutive nodes, keep the
 // dense layout.
-bool compact_fields(const lbmp_mp* h) { return h->variant == 3 || h->variant == 4; }
+bool compact_fields(const lbmp_mp* h) { return h->variant == 3 || h->variant == 4 || h->variant == 7; }
 
 // Fill the device geometry table for the current (K, gsz).
 template <typename T>
@@ -1685,7 +1730,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
         d.ntile = ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3-6: one block per K tiles
+        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3-7: one block per K tiles
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -1751,7 +1796,7 @@ lbmp_status autotune(lbmp_mp* h) {
         const int nread = sscanf(env, "%d,%d,%d", &v, &K, &gs);
         const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
         const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
-        const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || (v == 4 && K == 2) ||
+        const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || ((v == 4 || v == 7) && K == 2) ||
                           ((v == 5 || v == 6) && K == 2 && full_rows(h))) &&
                          gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
         if (nread == 3 && (ok01 || ok2 || ok3)) {
@@ -1764,7 +1809,8 @@ lbmp_status autotune(lbmp_mp* h) {
                                  "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
                                  "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles), or variant 4 (FP32 only) with K = 2 "
                                  "(z-planes per block), or variants 5, 6 (variants 3, 4 with full rows: FP32, nx = 64 in every "
-                                 "geometry) with K = 2; at most 64 species per block for 3-6");
+                                 "geometry) with K = 2, or variant 7 (variant 4 with lane compaction, FP32) with K = 2; "
+                                 "at most 64 species per block for 3-7");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1795,7 +1841,10 @@ lbmp_status autotune(lbmp_mp* h) {
         for (int gs : {2, 4, 8, 16, 32, 64})
             for (int K : {1, 2}) {
                 if (gs <= maxS || gs == 2) cand.push_back({K, gs, 3});
-                if (K == 2 && (gs <= maxS || gs == 2)) cand.push_back({K, gs, 4});
+                if (K == 2 && (gs <= maxS || gs == 2)) {
+                    cand.push_back({K, gs, 4});
+                    cand.push_back({K, gs, 7});
+                }
                 if (K == 2 && (gs <= maxS || gs == 2) && full_rows(h)) {
                     cand.push_back({K, gs, 5});
                     cand.push_back({K, gs, 6});
