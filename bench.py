@@ -90,7 +90,8 @@ def traffic_record(key: str):
 
 KERNELS = {0: ("direct", "k_mp_step"), 1: ("lds-box", "k_mp_step_box"), 2: ("z-march", "k_mp_march"),
            3: ("lds-dma", "k_mp_dma"), 4: ("lds-dma-zpair", "k_mp_dma"),
-           5: ("lds-dma-rows", "k_mp_dma"), 6: ("lds-dma-zpair-rows", "k_mp_dma")}
+           5: ("lds-dma-rows", "k_mp_dma"), 6: ("lds-dma-zpair-rows", "k_mp_dma"),
+           7: ("lds-dma-zpair-lanes", "k_mp_dma")}
 
 
 def rocprof_summary(root: str) -> dict:
