@@ -328,3 +328,106 @@ def test_uptake_matches_dense_chain(orc, pd):
     mob, ads = chain.dense_chain_uptake(m, u, 0.7, 0.06, pd, T)
     assert np.abs(r["mobile"] - mob).max() < 1e-13
     assert np.abs(r["adsorbed"] - ads).max() < 1e-13
+
+
+# ---------------------------------------------------------------- flow off the slit
+def _duct_series(W: int, g: float, nu: float, nterms: int = 200) -> np.ndarray:
+    """Steady laminar flow along x in a W x W square duct (walls at y, z = 0
+    and W), nu lap u = -g, as the Fourier series of the textbook rectangular
+    duct solution, at the node centres y, z = 1/2 .. W - 1/2 (half-way
+    walls). Returned as [z, y]."""
+    c = np.arange(W) + 0.5
+    Z, Y = np.meshgrid(c, c, indexing="ij")
+    a = float(W)
+    u = Y * (a - Y) / 2
+    for n in range(1, 2 * nterms, 2):
+        u -= (4 * a * a / (n ** 3 * math.pi ** 3) * np.sin(n * math.pi * Y / a)
+              * np.cosh(n * math.pi * (Z - a / 2) / a) / np.cosh(n * math.pi / 2))
+    return g / nu * u
+
+
+def test_bgk_square_duct_against_series(orc):
+    """Sec. I, Eq. 6 off the slit: a square duct has walls normal to y and to z,
+    so in-plane and out-of-plane links both carry the wall shear. The BGK
+    profile (tau = 1, nu = 1/6) must differ from the continuum series by a
+    bounded multiple of g at every node — second-order convergence, the error
+    relative to u_max falling as 1/W^2 — and be symmetric under y <-> z."""
+    g, nu = 1e-6, 1.0 / 6.0
+    errs = []
+    for W in (12, 24):
+        m = np.zeros((W + 2, W + 2, 1), np.uint8)
+        m[0] = m[-1] = 1
+        m[:, 0] = m[:, -1] = 1
+        r = orc.bgk(m, 1.0, [g, 0, 0], 1e-11, 400000)
+        assert r["converged"]
+        ux = r["u"][0, 1:-1, 1:-1, 0]
+        ex = _duct_series(W, g, nu)
+        dev = ux - ex
+        assert np.abs(dev).max() < 0.3 * g, W          # measured 0.19 g (W = 12), 0.22 g (W = 24)
+        assert np.abs(ux - ux.T).max() < 1e-11 * ex.max()
+        assert np.abs(r["u"][1:]).max() < 1e-6 * ex.max()  # no cross flow (rounding: 1.6e-7)
+        errs.append(np.abs(dev).max() / ex.max())
+    assert 3.0 < errs[0] / errs[1] < 5.0                # second order: 3.5 measured
+
+
+def _bgk_fixed_steps(orc, m, g, steps=300):
+    # a fixed number of steps (tol 0 never stops early): the symmetries hold at every step
+    r = orc.bgk(m, 1.0, g, 0.0, steps, check_every=steps + 1)
+    return r["u"]
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (0, 2), (1, 2)], ids=["x<->y", "x<->z", "y<->z"])
+def test_bgk_exchange_symmetry(orc, a, b):
+    """A porous mask symmetric under exchanging axes a and b, driven by a
+    force with equal a and b components, has u_a(r) = u_b(r') at the mirrored
+    node r': every in-plane D3Q19 link must be paired with its true image."""
+    n = 8
+    m = inputs.random_mask(n, n, n, 0.25, seed=40 + a + b)
+    ax = {0: 2, 1: 1, 2: 0}                             # velocity component -> array axis
+    perm = [0, 1, 2]
+    perm[ax[a]], perm[ax[b]] = ax[b], ax[a]
+    m = m | m.transpose(perm)
+    gv = np.full(3, 3e-5)
+    gv[3 - a - b] = 1.1e-5                              # a different value on the third axis
+    u = _bgk_fixed_steps(orc, m, gv)
+    scale = np.abs(u).max()
+    assert scale > 1e-6
+    assert np.abs(u[a] - u[b].transpose(perm)).max() <= 1e-12 * scale
+    c = 3 - a - b
+    assert np.abs(u[c] - u[c].transpose(perm)).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2], ids=["x", "y", "z"])
+def test_bgk_mirror_symmetry(orc, axis):
+    """Reflecting the mask through a lattice plane normal to `axis` and
+    reversing that force component reverses the velocity component along the
+    axis and mirrors the others: catches a sign error in any link."""
+    m = inputs.random_mask(7, 6, 5, 0.3, seed=9)
+    g = np.array([2e-5, 1.3e-5, 0.7e-5])
+    u = _bgk_fixed_steps(orc, m, g)
+    arr = 2 - axis
+    n = m.shape[arr]
+
+    def refl(f):
+        return np.roll(np.flip(f, axis=arr), 1, axis=arr)  # index i -> (n - i) mod n
+    g2 = g.copy()
+    g2[axis] = -g2[axis]
+    u2 = _bgk_fixed_steps(orc, np.ascontiguousarray(refl(m)), g2)
+    scale = np.abs(u).max()
+    for c in range(3):
+        sign = -1.0 if c == axis else 1.0
+        assert np.abs(u2[c] - sign * refl(u[c])).max() <= 1e-12 * scale, c
+    assert n > 2
+
+
+def test_bgk_enclosed_node_has_zero_mean_velocity(orc):
+    """A fluid node whose 18 neighbours are solid: bounce-back returns all its
+    momentum, so u(t+1) = -u(t) exactly and the two-step average of the
+    velocity is zero however the force points."""
+    m = np.ones((5, 5, 5), np.uint8)
+    m[2, 2, 2] = 0
+    m[0, 0, 0] = 0     # a second pocket, so the residual has a scale
+    g = np.array([3e-5, -2e-5, 1e-5])
+    r = orc.bgk(m, 1.0, g, 1e-10, 1000)
+    # |u(t)| = |g|/2 every step; the average cancels to rounding (1.5e-18 measured)
+    assert np.abs(r["u"]).max() <= 1e-10 * np.abs(g).max()
