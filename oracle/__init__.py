@@ -16,4 +16,4 @@ Modules:
 """
 from . import core  # noqa: F401
 from .core import (bgk, build, classify, d_of_t, lambda_from, links,  # noqa: F401
-                   propagate, threads, uptake, vacf)
+                   propagate, set_threads, threads, uptake, vacf)

@@ -54,8 +54,9 @@ def _load():
     lib.orc_uptake.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, c_double, c_double, c_int,
                                c_long, _dp, _dp]
     lib.orc_threads.argtypes = []
+    lib.orc_set_threads.argtypes = [c_int]
     for f in ("orc_classify", "orc_links", "orc_step", "orc_propagate", "orc_vacf", "orc_bgk",
-              "orc_uptake", "orc_threads"):
+              "orc_uptake", "orc_threads", "orc_set_threads"):
         getattr(lib, f).restype = c_int
     _lib = lib
     return lib
@@ -64,6 +65,11 @@ def _load():
 def threads() -> int:
     """OpenMP thread count the oracle runs on."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Run later oracle calls on n OpenMP threads; returns the new count."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _mask(mask):

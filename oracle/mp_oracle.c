@@ -444,3 +444,13 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* run the following calls on n OpenMP threads (results do not depend on it) */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#endif
+    return orc_threads();
+}

@@ -128,6 +128,24 @@ def _torch_cuda():
     return torch
 
 
+def _enter(stream, *tensors):
+    """Order work queued on `stream` after the caller's current stream (which
+    produced the tensors and the workspaces' previous contents), and tell the
+    caching allocator that `stream` uses the tensors."""
+    import torch
+    stream.wait_stream(torch.cuda.current_stream())
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
+def _leave(stream):
+    """Order the caller's current stream after the work just queued on `stream`
+    (so results can be used there without an explicit synchronisation)."""
+    import torch
+    torch.cuda.current_stream().wait_stream(stream)
+
+
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
@@ -184,6 +202,7 @@ def lb_flow_solve(mask, tau: float = 1.0, force=(0.0, 0.0, 0.0), tol: float = 1e
     ws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
     scratch = torch.empty(sb.value, dtype=torch.uint8, device="cuda")
     stream = stream or torch.cuda.Stream()
+    _enter(stream, ws, scratch)
     f = (ctypes.c_double * 3)(*force)
     h = ctypes.c_void_p()
     steps, res = ctypes.c_int64(), ctypes.c_double()
@@ -211,6 +230,7 @@ def lb_flow_from_velocity(mask, u, periodic=(1, 1, 1), iface_nbhd: int = 18, str
     _check(_lib.lb_flow_workspace_bytes(ctypes.byref(g), ctypes.byref(pb), None))
     ws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
     stream = stream or torch.cuda.Stream()
+    _enter(stream, ws)
     h = ctypes.c_void_p()
     _check(_lib.lb_flow_from_velocity(ctypes.byref(g), _ptr(ua), ctypes.c_void_p(ws.data_ptr()),
                                       pb.value, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
@@ -274,6 +294,7 @@ def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stre
     _check(_lib.mp_workspace_bytes(fl, sps, n, precision, max_steps, ctypes.byref(nb)))
     ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
     stream = stream or torch.cuda.Stream()
+    _enter(stream, ws)
     h = ctypes.c_void_p()
     _check(getattr(_lib, _entry)(fl, sps, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()), nb.value,
                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
@@ -297,7 +318,9 @@ def mp_uptake(mp: MP, geom: int = 0, t0: int = 0, count: int | None = None) -> d
 
 
 def mp_step_n(mp: MP, n: int):
-    """Queue n steps on the handle's stream (asynchronous)."""
+    """Queue n steps on the handle's stream (asynchronous; ordered after the
+    caller's current stream)."""
+    _enter(mp.stream)
     _check(_lib.mp_step_n(mp.handle, int(n)))
 
 
@@ -363,6 +386,7 @@ class Surrogate:
         _check(_lib.sg_workspace_bytes(batch_max, ctypes.byref(nb)))
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
         self.stream = stream or torch.cuda.Stream()
+        _enter(self.stream, self.ws)
         self.batch_max = batch_max
         h = ctypes.c_void_p()
         _check(_lib.sg_create(batch_max, seed, ctypes.c_void_p(self.ws.data_ptr()), nb.value,
@@ -390,6 +414,7 @@ class Surrogate:
     def train_step(self, x, y, idx, B: int, lr: float, want_loss: bool = False):
         """x, y: torch float32 CUDA tensors (n, 6), (n,); idx: int32 CUDA tensor (>= B) or None."""
         loss = ctypes.c_float()
+        _enter(self.stream, x, y, idx)
         _check(_lib.sg_train_step(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                   ctypes.c_void_p(idx.data_ptr()) if idx is not None else None, int(B),
                                   float(lr), ctypes.byref(loss) if want_loss else None))
@@ -398,17 +423,22 @@ class Surrogate:
     def gradients(self, x, y, B: int):
         g = np.zeros(self.n_params, dtype=np.float32)
         loss = ctypes.c_float()
+        _enter(self.stream, x, y)
         _check(_lib.sg_gradients(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                  int(B), _ptr(g), ctypes.byref(loss)))
         return g, loss.value
 
     def predict(self, x, out=None):
-        """x: torch float32 CUDA tensor (n, 6) -> torch float32 CUDA tensor (n,)."""
+        """x: torch float32 CUDA tensor (n, 6) -> torch float32 CUDA tensor (n,).
+        Runs on the handle's stream after the caller's current stream's work;
+        the current stream waits for the result."""
         torch = _torch_cuda()
         n = x.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _enter(self.stream, x, out)
         _check(_lib.sg_predict(self.handle, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
+        _leave(self.stream)
         return out
 
     def sync(self):

@@ -18,6 +18,7 @@ from . import inputs
 
 N, RADIUS, POROSITY, N_SPECIES, SEED = 256, 8, 0.4, 16, 2024
 D_B, PECLET = 1e-2, 10.0
+G_REF, FLOW_TOL = 1e-6, 1e-10  # reference force of the flow solve, steady-state tolerance
 
 
 def build(lb, n: int = N, radius: float = RADIUS, porosity: float = POROSITY, n_species: int = N_SPECIES,
@@ -28,7 +29,7 @@ def build(lb, n: int = N, radius: float = RADIUS, porosity: float = POROSITY, n_
     if log:
         log(f"sphere pack {n}^3: {time.time() - t0:.1f}s")
     t0 = time.time()
-    ref = lb.lb_flow_solve(mask, 1.0, [1e-6, 0.0, 0.0], 1e-6, 200000)
+    ref = lb.lb_flow_solve(mask, 1.0, [G_REF, 0.0, 0.0], FLOW_TOL, 400000)
     u = ref.velocity()
     ref.free()
     vbar = float(u[0][mask == 0].mean())

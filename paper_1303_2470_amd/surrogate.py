@@ -30,10 +30,13 @@ D_B = 0.01
 SPECIES_PER_GROUP = 8
 T_SAMPLES = 32
 G_REF = 1e-6
-DOMAIN = {  # training domain of the features (fallback outside it)
+DOMAIN = {  # training domain of the features, in feature order (fallback outside it)
     "porosity": (0.3, 0.7), "specific_surface": (0.0, 1.0), "peclet": (0.0, 100.0),
     "log10_ka": (-4.0, -1.0), "log10_kd": (-4.0, -1.0),
+    # sampled times run from 1 to 10 R^2 / D_b, at most 1e5 (R <= 10)
+    "log10_t": (0.0, 5.0),
 }
+MEDIUM_SHAPE = (N_LAT, N_LAT, N_LAT)  # Pe and N_I/N are defined on 64^3 samples
 
 
 def group_params(seed: int) -> dict:
@@ -110,6 +113,24 @@ def build_dataset(lb, seeds, batch: int = 8, log=None):
         Y.append(y)
         infos.append(info)
     return np.concatenate(X), np.concatenate(Y), infos
+
+
+def query_features(shape, n_fluid: int, n_iface: int, peclet: float, k_a, k_d, times):
+    """Feature rows (porosity, N_I/N, Pe, log10 k_a, log10 k_d, log10 t) of a
+    query, species-major, or None when the network cannot answer it: a medium
+    not of the training shape, a rate or time without a logarithm (k <= 0,
+    t < 1), or any feature outside the training domain."""
+    k_a = np.atleast_1d(np.asarray(k_a, dtype=np.float64))
+    k_d = np.atleast_1d(np.asarray(k_d, dtype=np.float64))
+    times = np.atleast_1d(np.asarray(times, dtype=np.float64))
+    if tuple(shape) != MEDIUM_SHAPE:
+        return None
+    if not ((k_a > 0).all() and (k_d > 0).all() and (times >= 1).all() and np.isfinite(peclet)):
+        return None
+    n = float(np.prod(shape))
+    feats = np.array([[n_fluid / n, n_iface / n, peclet, math.log10(a), math.log10(d), math.log10(t)]
+                      for a, d in zip(k_a, k_d) for t in times])
+    return feats if in_domain(feats).all() else None
 
 
 def in_domain(features: np.ndarray) -> np.ndarray:
@@ -236,9 +257,8 @@ def query(lb, sg, mask: np.ndarray, peclet: float, k_a, k_d, times, velocity: np
     fl = lb.lb_flow_from_velocity(mask, np.zeros((3,) + mask.shape))
     _, nf, ni = fl.classes()
     fl.free()
-    feats = np.array([[nf / mask.size, ni / mask.size, peclet, math.log10(a), math.log10(d), math.log10(t)]
-                      for a, d in zip(k_a, k_d) for t in times])
-    ok = in_domain(feats).all() and (k_a > 0).all() and (times >= 1).all()
+    feats = query_features(mask.shape, nf, ni, peclet, k_a, k_d, times)
+    ok = feats is not None
     if ok and table is not None:
         ok = bool(trusted(feats, table, tol).all())
     if ok:

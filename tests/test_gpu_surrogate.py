@@ -169,7 +169,7 @@ def test_dataset_rows_and_fallback(lb):
     assert surrogate.in_domain(X).all()
     assert info["steps"] == surrogate.sample_times(4)[-1]
     sg = lb.Surrogate(256, seed=1)
-    mask = inputs.sphere_pack(32, 4, 0.5, seed=3)
+    mask = inputs.sphere_pack(64, 4, 0.5, seed=3)   # the training media size
     u = inputs.random_velocity(mask, 0.005, seed=4)
     D, how = surrogate.query(lb, sg, mask, 10.0, [0.5], [0.01], [1, 10, 100], velocity=u)  # k_a out of domain
     assert how == "method"
@@ -190,7 +190,7 @@ def test_error_gated_fallback(lb):
     the method runs and equals a direct run."""
     from paper_1303_2470_amd import inputs, surrogate
     sg = lb.Surrogate(256, seed=1)
-    mask = inputs.sphere_pack(32, 4, 0.5, seed=3)
+    mask = inputs.sphere_pack(64, 4, 0.5, seed=3)   # the training media size
     u = inputs.random_velocity(mask, 0.005, seed=4)
     nt, npe = len(surrogate.T_EDGES) - 1, len(surrogate.PE_EDGES) - 1
     table = np.full((nt, npe), 0.01)
@@ -209,4 +209,27 @@ def test_error_gated_fallback(lb):
     assert how == "method"
     mp.free()
     fl.free()
+    sg.free()
+
+
+def test_predict_orders_after_current_stream(lb):
+    """Inputs produced by device kernels still running on the caller's stream:
+    predict (on the handle's own stream) waits for them, and the caller's
+    stream waits for the predictions."""
+    import torch
+    sg = lb.Surrogate(1024, seed=3)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x0 = torch.rand((4096, 6), device="cuda", generator=g)
+    torch.cuda.synchronize()
+    ref = sg.predict(x0.clone())
+    sg.sync()
+    ref = ref.cpu()
+    # a slow producer on the current stream: x is written only after the matmuls
+    y = torch.rand((2048, 2048), device="cuda", generator=g)
+    for _ in range(30):
+        y = (y @ y) / 2048.0
+    x = x0 + 0.0 * y[:1, :6]
+    out = sg.predict(x)
+    got = (out * 1.0).cpu()          # consumed on the current stream without a sync
+    assert torch.equal(got, ref)
     sg.free()

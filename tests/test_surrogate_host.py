@@ -53,3 +53,25 @@ def test_split_groups_disjoint_whole_groups():
         assert a[m].all() or b[m].all()
     a2, _ = S.split_groups(X, seed=3)
     assert np.array_equal(a, a2)
+
+
+def test_query_features_domain_guards():
+    """Queries the network cannot answer give no feature rows (the method then
+    runs): no logarithm for k_a = 0 or t = 0, times beyond the training
+    horizon of 1e5 steps, a medium not 64^3, features outside the domain."""
+    shape = (64, 64, 64)
+    n = 64 ** 3
+    ok = S.query_features(shape, int(0.5 * n), int(0.1 * n), 20.0, [1e-3, 1e-2], [1e-3, 1e-4], [1, 10, 1000])
+    assert ok.shape == (6, 6) and S.in_domain(ok).all()
+    assert np.allclose(ok[0], [0.5, 0.1, 20.0, -3.0, -3.0, 0.0], atol=1e-6)
+    bad = [
+        dict(k_a=[0.0], k_d=[1e-3], times=[10]),         # k_a = 0: allowed by the method, no log
+        dict(k_a=[1e-3], k_d=[1e-3], times=[0]),         # t = 0
+        dict(k_a=[1e-3], k_d=[1e-3], times=[200000]),    # beyond 1e5
+        dict(k_a=[1e-3], k_d=[0.5], times=[10]),         # log10 k_d > -1
+    ]
+    for b in bad:
+        assert S.query_features(shape, int(0.5 * n), int(0.1 * n), 20.0, **b) is None, b
+    assert S.query_features((32, 32, 32), 16000, 3000, 20.0, [1e-3], [1e-3], [10]) is None
+    assert S.query_features(shape, int(0.9 * n), int(0.1 * n), 20.0, [1e-3], [1e-3], [10]) is None
+    assert S.query_features(shape, int(0.5 * n), int(0.1 * n), 150.0, [1e-3], [1e-3], [10]) is None
