@@ -85,6 +85,25 @@ lbmp_status lb_flow_solve(const lbmp_geometry* g, double tau, const double force
                           int64_t max_steps, int check_every,
                           void* dev_ws, size_t ws_bytes, void* dev_scratch, size_t scratch_bytes,
                           void* hip_stream, lbmp_flow** out, int64_t* steps_done, double* residual);
+/* The same solve without a scratch workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation). The populations, velocity history and
+ * residual partials live in a file-scope device array of
+ * LBMP_STATIC_SCRATCH_BYTES (128 MiB), which each GPU the library runs on
+ * holds until the process ends; no hipMalloc, hipFree or allocating routine
+ * is called. The caller still passes the persistent workspace dev_ws (the
+ * returned handle lives there, as with lb_flow_solve). Arguments, results and
+ * errors are those of lb_flow_solve, plus LBMP_ENOMEM for a lattice of more
+ * than lb_flow_static_max_nodes() nodes (checked before any device work).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (two host threads, or two streams) race and must be serialised by
+ * the caller. */
+#define LBMP_STATIC_SCRATCH_BYTES (128u << 20)
+lbmp_status lb_flow_solve_static(const lbmp_geometry* g, double tau, const double force[3], double tol,
+                                 int64_t max_steps, int check_every, void* dev_ws, size_t ws_bytes,
+                                 void* hip_stream, lbmp_flow** out, int64_t* steps_done, double* residual);
+/* Largest lattice (nx*ny*nz) lb_flow_solve_static accepts. */
+int64_t lb_flow_static_max_nodes(void);
 /* A flow handle from a given velocity field (host, FP64, [3][N] SoA, x then y
  * then z component; values on solid nodes are ignored). Uses dev_ws like
  * lb_flow_solve (persistent part only). */

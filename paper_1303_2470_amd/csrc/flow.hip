@@ -7,6 +7,8 @@
 // population of the node itself when the upstream node is solid), forms the
 // density and the force-corrected velocity u = (sum f c)/rho + g/2, and
 // relaxes towards the equilibrium with the Guo source term.
+#include <mutex>
+
 #include "lbmp_internal.hpp"
 
 namespace lbmp {
@@ -166,12 +168,12 @@ static size_t scratch_bytes_for(int64_t N) {
 using namespace lbmp;
 
 extern "C" lbmp_status lb_flow_workspace_bytes(const lbmp_geometry* g, size_t* persistent,
-                                               size_t* scratch) {
+                                               size_t* scratch_out) {
     if (!g || g->nx <= 0 || g->ny <= 0 || g->nz <= 0)
         return fail(LBMP_EINVAL, "invalid geometry");
     int64_t N = (int64_t)g->nx * g->ny * g->nz;
     if (persistent) *persistent = align_up(sizeof(lbmp_flow)) + geometry_bytes(N);
-    if (scratch) *scratch = scratch_bytes_for(N);
+    if (scratch_out) *scratch_out = scratch_bytes_for(N);
     return LBMP_OK;
 }
 
@@ -202,11 +204,13 @@ static lbmp_status make_flow(const lbmp_geometry* g, void* dev_ws, size_t ws_byt
     return LBMP_OK;
 }
 
-extern "C" lbmp_status lb_flow_solve(const lbmp_geometry* g, double tau, const double force[3],
-                                     double tol, int64_t max_steps, int check_every, void* dev_ws,
-                                     size_t ws_bytes, void* dev_scratch, size_t scratch_bytes,
-                                     void* hip_stream, lbmp_flow** out, int64_t* steps_done,
-                                     double* residual) {
+// The solve of lb_flow_solve and lb_flow_solve_static: populations, velocity
+// history and residual partials in dev_scratch (scratch_bytes long); nothing
+// in dev_scratch needs to start at zero.
+static lbmp_status flow_solve(const lbmp_geometry* g, double tau, const double force[3], double tol,
+                              int64_t max_steps, int check_every, void* dev_ws, size_t ws_bytes,
+                              void* dev_scratch, size_t scratch_bytes, void* hip_stream, lbmp_flow** out,
+                              int64_t* steps_done, double* residual) {
     if (!out) return fail(LBMP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBMP_EINVAL, "tau must exceed 1/2");
@@ -288,6 +292,78 @@ extern "C" lbmp_status lb_flow_solve(const lbmp_geometry* g, double tau, const d
     if (!conv) return fail(LBMP_ENOTCONV, "flow not converged after %lld steps (residual %.3e)",
                            (long long)step, resv);
     return LBMP_OK;
+}
+
+extern "C" lbmp_status lb_flow_solve(const lbmp_geometry* g, double tau, const double force[3],
+                                     double tol, int64_t max_steps, int check_every, void* dev_ws,
+                                     size_t ws_bytes, void* dev_scratch, size_t scratch_bytes,
+                                     void* hip_stream, lbmp_flow** out, int64_t* steps_done,
+                                     double* residual) {
+    return flow_solve(g, tau, force, tol, max_steps, check_every, dev_ws, ws_bytes, dev_scratch, scratch_bytes,
+                      hip_stream, out, steps_done, residual);
+}
+
+// ---------------------------------------------------------------- no-allocation solve
+// lb_flow_solve_static takes its scratch from a file-scope device array
+// instead of a caller workspace, for callers that cannot allocate device
+// memory. Each GPU holds its own copy of the array (at its own address) until
+// the process ends; the host-side name is not a device address, so the
+// address is taken once per device with hipGetSymbolAddress and used from
+// then on.
+namespace lbmp {
+static __device__ __align__(256) unsigned char scratch[LBMP_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES];  // per device, null until first use there
+
+static lbmp_status static_scratch(void** ptr) {
+    int dev = -1;
+    LBMP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBMP_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBMP_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return LBMP_OK;
+}
+}  // namespace lbmp
+
+extern "C" lbmp_status lb_flow_solve_static(const lbmp_geometry* g, double tau, const double force[3],
+                                            double tol, int64_t max_steps, int check_every, void* dev_ws,
+                                            size_t ws_bytes, void* hip_stream, lbmp_flow** out,
+                                            int64_t* steps_done, double* residual) {
+    if (!out) return fail(LBMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    lbmp_status st = validate_geometry(g);
+    if (st != LBMP_OK) return st;
+    const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    const size_t need = scratch_bytes_for(N);
+    if (need > (size_t)LBMP_STATIC_SCRATCH_BYTES)
+        return fail(LBMP_ENOMEM, "lattice of %lld nodes needs %zu scratch bytes; the static scratch holds %zu "
+                    "(at most %lld nodes)", (long long)N, need, (size_t)LBMP_STATIC_SCRATCH_BYTES,
+                    (long long)lb_flow_static_max_nodes());
+    void* p = nullptr;
+    st = static_scratch(&p);
+    if (st != LBMP_OK) return st;
+    return flow_solve(g, tau, force, tol, max_steps, check_every, dev_ws, ws_bytes, p,
+                      (size_t)LBMP_STATIC_SCRATCH_BYTES, hip_stream, out, steps_done, residual);
+}
+
+extern "C" int64_t lb_flow_static_max_nodes(void) {
+    // scratch_bytes_for is 376 bytes per node plus alignment and the residual
+    // partials; the largest N that fits
+    int64_t lo = 0, hi = (int64_t)LBMP_STATIC_SCRATCH_BYTES / 376 + 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (scratch_bytes_for(mid) <= (size_t)LBMP_STATIC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 extern "C" lbmp_status lb_flow_from_velocity(const lbmp_geometry* g, const double* u_host,

@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["lbmp_last_error", "lbmp_version", "lb_flow_workspace_bytes", "lb_flow_solve",
-           "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
+           "lb_flow_solve_static", "lb_flow_static_max_nodes", "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
            "mp_workspace_bytes", "mp_init", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
            "mp_uptake_init", "mp_uptake",
            "mp_state", "mp_profile_steps", "mp_free", "sg_param_count", "sg_workspace_bytes",
@@ -81,6 +81,9 @@ def load_library(path: str = LIB_PATH):
         "lb_flow_workspace_bytes": ([P(Geometry), P(sz), P(sz)], i32),
         "lb_flow_solve": ([P(Geometry), dbl, P(dbl), dbl, i64, i32, vp, sz, vp, sz, vp, P(vp),
                            P(i64), P(dbl)], i32),
+        "lb_flow_solve_static": ([P(Geometry), dbl, P(dbl), dbl, i64, i32, vp, sz, vp, P(vp), P(i64),
+                                  P(dbl)], i32),
+        "lb_flow_static_max_nodes": ([], i64),
         "lb_flow_from_velocity": ([P(Geometry), vp, vp, sz, vp, P(vp)], i32),
         "lb_flow_velocity": ([vp, vp], i32),
         "lb_flow_classes": ([vp, vp, P(i64), P(i64)], i32),
@@ -216,6 +219,39 @@ def lb_flow_solve(mask, tau: float = 1.0, force=(0.0, 0.0, 0.0), tol: float = 1e
         return Flow(h, ws, m, g, stream, steps.value, res.value, False)
     _check(st)
     return Flow(h, ws, m, g, stream, steps.value, res.value, True)
+
+
+def lb_flow_solve_static(mask, tau: float = 1.0, force=(0.0, 0.0, 0.0), tol: float = 1e-10,
+                         max_steps: int = 200000, check_every: int = 100, periodic=(1, 1, 1),
+                         iface_nbhd: int = 18, stream=None, ws=None, allow_unconverged: bool = False) -> Flow:
+    """lb_flow_solve without a scratch workspace (C-ABI lb_flow_solve_static):
+    the solve's scratch is the library's static device array. `ws`, the
+    persistent workspace (uint8 CUDA tensor of lb_flow_workspace_bytes), may
+    be passed in so that the call itself allocates nothing."""
+    torch = _torch_cuda()
+    load_library()
+    g, m = _geometry(mask, periodic, iface_nbhd)
+    pb = ctypes.c_size_t()
+    _check(_lib.lb_flow_workspace_bytes(ctypes.byref(g), ctypes.byref(pb), None))
+    if ws is None:
+        ws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
+    stream = stream or torch.cuda.Stream()
+    _enter(stream, ws)
+    f = (ctypes.c_double * 3)(*force)
+    h = ctypes.c_void_p()
+    steps, res = ctypes.c_int64(), ctypes.c_double()
+    st = _lib.lb_flow_solve_static(ctypes.byref(g), tau, f, tol, max_steps, check_every,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h),
+                                   ctypes.byref(steps), ctypes.byref(res))
+    if st == -4 and allow_unconverged:
+        return Flow(h, ws, m, g, stream, steps.value, res.value, False)
+    _check(st)
+    return Flow(h, ws, m, g, stream, steps.value, res.value, True)
+
+
+def lb_flow_static_max_nodes() -> int:
+    return int(load_library().lb_flow_static_max_nodes())
 
 
 def lb_flow_from_velocity(mask, u, periodic=(1, 1, 1), iface_nbhd: int = 18, stream=None) -> Flow:
