@@ -29,8 +29,11 @@ LINKS = np.array(_LINKS, dtype=np.int64)           # (18, 3) as (cx, cy, cz)
 WEIGHTS = np.array([1.0 / 18 if sum(abs(v) for v in c) == 1 else 1.0 / 36 for c in _LINKS])
 
 
-def link_probs(mask, u, lam):
-    """p_i(r) for every node and the 18 links: array (18, nz, ny, nx)."""
+def link_probs(mask, u, lam, bmu=None):
+    """p_i(r) for every node and the 18 links: array (18, nz, ny, nx).
+
+    bmu: beta mu^ex(r) of a charged tracer; the diffusive part of a hop from
+    r to r + c is then scaled by exp(-(bmu(r + c) - bmu(r)) / 2)."""
     mask = np.asarray(mask).astype(bool)
     nz, ny, nx = mask.shape
     if u is None:
@@ -42,7 +45,11 @@ def link_probs(mask, u, lam):
         # destination r + c fluid?
         dest_solid = np.roll(mask, shift=(-cz, -cy, -cx), axis=(0, 1, 2))
         cu = cx * ux + cy * uy + cz * uz
-        pk = WEIGHTS[k] * (lam / 2 + 3 * cu + 4.5 * cu * cu - 1.5 * usq)
+        diff = lam / 2
+        if bmu is not None:
+            dest_mu = np.roll(bmu, shift=(-cz, -cy, -cx), axis=(0, 1, 2))
+            diff = lam / 2 * np.exp(-(dest_mu - bmu) / 2)
+        pk = WEIGHTS[k] * (diff + 3 * cu + 4.5 * cu * cu - 1.5 * usq)
         p[k] = np.where(mask | dest_solid, 0.0, pk)
     return p
 
@@ -65,17 +72,22 @@ def _states(mask, nbhd):
     return fluid, iface
 
 
-def stationary_weights(mask, pa, pd, nbhd=18):
-    """Eq. 11 weights (no excess chemical potential) over the chain's states:
-    first the mobile states (fluid nodes in index order), then the adsorbed
-    states (interfacial nodes in index order)."""
+def stationary_weights(mask, pa, pd, nbhd=18, bmu=None):
+    """Eq. 11 weights over the chain's states: first the mobile states (fluid
+    nodes in index order), then the adsorbed states (interfacial nodes in
+    index order); with an excess chemical potential each state of node r
+    carries the Boltzmann factor exp(-bmu(r))."""
     fluid, iface = _states(mask, nbhd)
     K = pa / pd
-    w = np.concatenate([np.ones(len(fluid)), K * np.ones(len(iface))])
+    if bmu is None:
+        bf = np.ones(np.asarray(mask).size)
+    else:
+        bf = np.exp(-np.asarray(bmu, dtype=np.float64).ravel())
+    w = np.concatenate([bf[fluid], K * bf[iface]])
     return w / w.sum()
 
 
-def transition_matrix(mask, u, lam, pa, pd, nbhd=18):
+def transition_matrix(mask, u, lam, pa, pd, nbhd=18, bmu=None):
     """The tracer chain on the states "mobile at a fluid node" (first N_F) and
     "adsorbed at an interfacial node" (next N_I), built link by link: M the
     transition matrix, B[g] its displacement-weighted version, C2[g] the
@@ -87,7 +99,7 @@ def transition_matrix(mask, u, lam, pa, pd, nbhd=18):
     S = nf + ni
     mob = {int(n): k for k, n in enumerate(fluid)}
     ads = {int(n): nf + k for k, n in enumerate(iface)}
-    p = link_probs(mask, u, lam).reshape(18, -1)
+    p = link_probs(mask, u, lam, bmu).reshape(18, -1)
     M = np.zeros((S, S))
     B = np.zeros((3, S, S))
     C2 = np.zeros((3, S))          # E[v_g^2 | state]
@@ -118,15 +130,15 @@ def transition_matrix(mask, u, lam, pa, pd, nbhd=18):
     return M, B, C2, nf
 
 
-def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18):
+def dense_chain_vacf(mask, u, lam, pa, pd, steps, nbhd=18, bmu=None):
     """Z_g(m), m = 0..steps, from the explicit transition matrix.
 
     Z(0) = E[v(0)^2]; Z(m >= 1) = pi0^T B M^(m-1) b, where M is the transition
     matrix, B the displacement-weighted transition matrix and b = B 1.
     Returns (Z (3, steps+1), V (3,)).
     """
-    M, B, C2, nf = transition_matrix(mask, u, lam, pa, pd, nbhd)
-    pi0 = stationary_weights(mask, pa, pd, nbhd)
+    M, B, C2, nf = transition_matrix(mask, u, lam, pa, pd, nbhd, bmu)
+    pi0 = stationary_weights(mask, pa, pd, nbhd, bmu)
     b = B.sum(axis=2)
     V = pi0 @ b.T
     Z = np.zeros((3, steps + 1))

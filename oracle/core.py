@@ -53,10 +53,16 @@ def _load():
                             _dp, _dp, ctypes.POINTER(c_long), ctypes.POINTER(c_double)]
     lib.orc_uptake.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, c_double, c_double, c_int,
                                c_long, _dp, _dp]
+    lib.orc_links_charged.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, vp, _dp]
+    lib.orc_propagate_charged.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, c_double, c_double,
+                                          c_int, vp, c_long, _dp, _dp]
+    lib.orc_vacf_charged.argtypes = [c_int, c_int, c_int, _u8, vp, c_double, c_double, c_double, c_int,
+                                     vp, c_long, c_int, _dp, _dp, _dp, _dp]
     lib.orc_threads.argtypes = []
     lib.orc_set_threads.argtypes = [c_int]
     for f in ("orc_classify", "orc_links", "orc_step", "orc_propagate", "orc_vacf", "orc_bgk",
-              "orc_uptake", "orc_threads", "orc_set_threads"):
+              "orc_uptake", "orc_threads", "orc_set_threads", "orc_links_charged",
+              "orc_propagate_charged", "orc_vacf_charged"):
         getattr(lib, f).restype = c_int
     _lib = lib
     return lib
@@ -105,40 +111,56 @@ def classify(mask, nbhd: int = 18) -> np.ndarray:
     return cls
 
 
-def links(mask, u, lam: float) -> np.ndarray:
-    """Link probabilities p_i(r) of Eq. 8, shape (19, nz, ny, nx); p_0 = 0."""
+def _bmu(bmu, shape):
+    """beta mu^ex per node (charged tracers), or (None, None) for a neutral one."""
+    if bmu is None:
+        return None, None
+    a = np.ascontiguousarray(bmu, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError("beta_mu_ex must be (nz, ny, nx)")
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def links(mask, u, lam: float, bmu=None) -> np.ndarray:
+    """Link probabilities p_i(r) of Eq. 8, shape (19, nz, ny, nx); p_0 = 0.
+    bmu: beta mu^ex(r) of a charged tracer (the Q term), or None."""
     m, nx, ny, nz = _mask(mask)
     ua, up = _vel(u, m.shape)
+    ba, bp = _bmu(bmu, m.shape)
     p = np.zeros((19,) + m.shape)
-    _load().orc_links(nx, ny, nz, m, up, lam, p)
+    _load().orc_links_charged(nx, ny, nz, m, up, lam, bp, p)
     return p
 
 
-def propagate(mask, u, lam: float, pa: float, pd: float, steps: int, X, Xa, nbhd: int = 18):
+def propagate(mask, u, lam: float, pa: float, pd: float, steps: int, X, Xa, nbhd: int = 18, bmu=None):
     """Propagate a (mobile, adsorbed) pair ``steps`` times (Eqs. 7, 9, 10)."""
     m, nx, ny, nz = _mask(mask)
     ua, up = _vel(u, m.shape)
+    ba, bp = _bmu(bmu, m.shape)
     X = np.array(X, dtype=np.float64, order="C", copy=True)
     Xa = np.array(Xa, dtype=np.float64, order="C", copy=True)
-    _load().orc_propagate(nx, ny, nz, m, up, lam, pa, pd, nbhd, steps, X, Xa)
+    _load().orc_propagate_charged(nx, ny, nz, m, up, lam, pa, pd, nbhd, bp, steps, X, Xa)
     return X, Xa
 
 
 def vacf(mask, u, lam: float, pa: float, pd: float, steps: int, qmask: int = 15,
-         nbhd: int = 18) -> dict:
+         nbhd: int = 18, bmu=None) -> dict:
     """Moment-propagation VACF for t = 0..steps (Eqs. 5, 11, 12).
 
+    bmu: beta mu^ex(r) of a charged tracer (Q term of Eq. 8, Boltzmann factor
+    of Eq. 11), or None for a neutral one.
     Returns a dict with ``Z`` (3, T+1), ``V`` (3,), ``mass`` (2, T+1) — mobile
     and adsorbed totals — and ``mom`` (3, T+1), the first-moment totals.
     """
     m, nx, ny, nz = _mask(mask)
     ua, up = _vel(u, m.shape)
+    ba, bp = _bmu(bmu, m.shape)
     T1 = steps + 1
     Z = np.zeros(3 * T1)
     V = np.zeros(3)
     mass = np.zeros(2 * T1)
     mom = np.zeros(3 * T1)
-    rc = _load().orc_vacf(nx, ny, nz, m, up, lam, pa, pd, nbhd, steps, qmask, Z, V, mass, mom)
+    rc = _load().orc_vacf_charged(nx, ny, nz, m, up, lam, pa, pd, nbhd, bp, steps, qmask, Z, V, mass, mom)
     if rc != 0:
         raise ValueError("oracle rejected the input (no fluid node, or p_d <= 0)")
     return {"Z": Z.reshape(3, T1), "V": V, "mass": mass.reshape(2, T1),

@@ -107,9 +107,16 @@ int orc_classify(int nx, int ny, int nz, const uint8_t* solid, int nbhd, int8_t*
 
 /* ---- link probabilities (Eq. 8) ---------------------------------------- */
 /* p[i*N + n] = probability to leave n along c_i, i = 1..18; p[0..N-1] = 0.
- * u: [3][N] velocity, or NULL for a fluid at rest. */
-int orc_links(int nx, int ny, int nz, const uint8_t* solid, const double* u,
-              double lambda, double* p)
+ * u: [3][N] velocity, or NULL for a fluid at rest.
+ * bmu: [N] excess chemical potential beta mu^ex(r) of the tracer (e.g. its
+ * charge times the electrostatic potential, over k_B T), or NULL (neutral).
+ * The diffusive term of Eq. 8 carries the factor
+ *   Q_i(r) = exp(-(beta mu^ex(r + c_i) - beta mu^ex(r)) / 2),
+ * so that at rest rho(r) p_i(r) = rho(r + c_i) p_-i(r + c_i) for the
+ * Boltzmann weights rho ~ exp(-beta mu^ex) of Eq. 11 (detailed balance);
+ * Q = 1 for a neutral tracer. */
+int orc_links_charged(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+                      double lambda, const double* bmu, double* p)
 {
     long N = (long)nx * ny * nz;
     #pragma omp parallel for schedule(static) if (N > 32768)
@@ -121,10 +128,17 @@ int orc_links(int nx, int ny, int nz, const uint8_t* solid, const double* u,
             long m = neighbour(nx, ny, nz, n, i);
             if (solid[n] || solid[m]) { p[(long)i * N + n] = 0.0; continue; }
             double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-            p[(long)i * N + n] = W[i] * (0.5 * lambda + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            double Q = bmu ? exp(-0.5 * (bmu[m] - bmu[n])) : 1.0;
+            p[(long)i * N + n] = W[i] * (0.5 * lambda * Q + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         }
     }
     return 0;
+}
+
+int orc_links(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+              double lambda, double* p)
+{
+    return orc_links_charged(nx, ny, nz, solid, u, lambda, NULL, p);
 }
 
 /* ---- one propagation step (Eqs. 7, 9, 10) ------------------------------ */
@@ -160,9 +174,10 @@ int orc_step(int nx, int ny, int nz, const int8_t* cls, const double* p,
 }
 
 /* ---- propagate a given (X, Xa) pair T steps in place -------------------- */
-int orc_propagate(int nx, int ny, int nz, const uint8_t* solid, const double* u,
-                  double lambda, double pa, double pd, int nbhd, long T,
-                  double* X, double* Xa)
+/* bmu: beta mu^ex per node for a charged tracer (orc_links_charged), or NULL */
+int orc_propagate_charged(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+                          double lambda, double pa, double pd, int nbhd, const double* bmu,
+                          long T, double* X, double* Xa)
 {
     long N = (long)nx * ny * nz;
     int8_t* cls = (int8_t*)malloc(N);
@@ -170,7 +185,7 @@ int orc_propagate(int nx, int ny, int nz, const uint8_t* solid, const double* u,
     double* Y = (double*)malloc(sizeof(double) * N);
     double* Ya = (double*)malloc(sizeof(double) * N);
     orc_classify(nx, ny, nz, solid, nbhd, cls);
-    orc_links(nx, ny, nz, solid, u, lambda, p);
+    orc_links_charged(nx, ny, nz, solid, u, lambda, bmu, p);
     for (long t = 0; t < T; ++t) {
         orc_step(nx, ny, nz, cls, p, pa, pd, X, Xa, Y, Ya);
         memcpy(X, Y, sizeof(double) * N);
@@ -178,6 +193,13 @@ int orc_propagate(int nx, int ny, int nz, const uint8_t* solid, const double* u,
     }
     free(cls); free(p); free(Y); free(Ya);
     return 0;
+}
+
+int orc_propagate(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+                  double lambda, double pa, double pd, int nbhd, long T,
+                  double* X, double* Xa)
+{
+    return orc_propagate_charged(nx, ny, nz, solid, u, lambda, pa, pd, nbhd, NULL, T, X, Xa);
 }
 
 /* ---- Uptake out of equilibrium (density propagated; Eqs. 7, 9, 10) ------ */
@@ -224,9 +246,11 @@ int orc_uptake(int nx, int ny, int nz, const uint8_t* solid, const double* u,
  * qmask selects the propagated pairs: bit 0 density, bits 1..3 x, y, z
  * moments (unselected outputs are left as zero).
  * Returns 0, or -1 when the lattice has no fluid node or p_d <= 0. */
-int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
-             double lambda, double pa, double pd, int nbhd, long T, int qmask,
-             double* Z, double* V, double* mass, double* mom)
+/* bmu: [N] beta mu^ex(r) (charged tracers: Eq. 8 with the Q_i of
+ * orc_links_charged, Eq. 11 with the factor exp(-beta mu^ex)), or NULL. */
+int orc_vacf_charged(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+                     double lambda, double pa, double pd, int nbhd, const double* bmu,
+                     long T, int qmask, double* Z, double* V, double* mass, double* mom)
 {
     long N = (long)nx * ny * nz;
     if (pd <= 0.0) return -1;
@@ -234,14 +258,21 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
     double* p = (double*)malloc(sizeof(double) * Q19 * N);
     double* tmp = (double*)malloc(sizeof(double) * N);
     orc_classify(nx, ny, nz, solid, nbhd, cls);
-    orc_links(nx, ny, nz, solid, u, lambda, p);
+    orc_links_charged(nx, ny, nz, solid, u, lambda, bmu, p);
 
     long nf = 0, ni = 0;
     for (long n = 0; n < N; ++n) { nf += cls[n] != 0; ni += cls[n] == 2; }
     if (nf == 0) { free(cls); free(p); free(tmp); return -1; }
     double K = pa / pd;                      /* Gamma/rho at equilibrium (Eq. 11) */
-    double Zpart = (double)nf + (double)ni * K;
-    double rho0 = 1.0 / Zpart;
+    /* Eq. 11: weight exp(-beta mu^ex(r)) of a mobile tracer at a fluid node,
+     * times (1 + K) on interfacial nodes; Zpart normalises the total to 1 */
+    double* rho0 = (double*)malloc(sizeof(double) * N);
+    for (long n = 0; n < N; ++n) tmp[n] = cls[n] ? (bmu ? exp(-bmu[n]) : 1.0) : 0.0;
+    double sF = nsum(tmp, N);
+    for (long n = 0; n < N; ++n) if (cls[n] != 2) tmp[n] = 0.0;
+    double sI = nsum(tmp, N);
+    double Zpart = sF + sI * K;
+    for (long n = 0; n < N; ++n) rho0[n] = cls[n] ? (bmu ? exp(-bmu[n]) : 1.0) / Zpart : 0.0;
 
     /* a_g(r) = sum_i p_i(r) c_ig: mean displacement of a mobile tracer at r */
     double* a = (double*)calloc(3 * N, sizeof(double));
@@ -260,13 +291,13 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
     /* mean velocity and Z(0) = <v_g(0)^2> over the initial weights */
     for (int g = 0; g < 3; ++g) {
         const int* cg = g == 0 ? CX : (g == 1 ? CY : CZ);
-        for (long n = 0; n < N; ++n) tmp[n] = cls[n] ? rho0 * a[g * N + n] : 0.0;
+        for (long n = 0; n < N; ++n) tmp[n] = cls[n] ? rho0[n] * a[g * N + n] : 0.0;
         V[g] = nsum(tmp, N);
         for (long n = 0; n < N; ++n) {
             double s = 0.0;
             if (cls[n])
                 for (int i = 1; i < Q19; ++i) s += p[(long)i * N + n] * cg[i] * cg[i];
-            tmp[n] = cls[n] ? rho0 * s : 0.0;
+            tmp[n] = cls[n] ? rho0[n] * s : 0.0;
         }
         Z[g * T1] = nsum(tmp, N);
         mom[g * T1] = V[g];
@@ -282,8 +313,8 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
         if (q == 0) {
             /* density: the initial weights themselves */
             for (long n = 0; n < N; ++n) {
-                X[n] = cls[n] ? rho0 : 0.0;
-                Xa[n] = cls[n] == 2 ? K * rho0 : 0.0;
+                X[n] = cls[n] ? rho0[n] : 0.0;
+                Xa[n] = cls[n] == 2 ? K * rho0[n] : 0.0;
             }
             mass[0] = nsum(X, N);
             mass[T1] = nsum(Xa, N);
@@ -301,7 +332,7 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
                 if (cls[n])
                     for (int i = 1; i < Q19; ++i) {
                         long src = neighbour(nx, ny, nz, n, opposite(i));
-                        if (cls[src]) v += rho0 * p[(long)i * N + src] * cg[i];
+                        if (cls[src]) v += rho0[src] * p[(long)i * N + src] * cg[i];
                     }
                 X[n] = v;
                 Xa[n] = 0.0;
@@ -324,9 +355,17 @@ int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
             memcpy(Xa, Ya, sizeof(double) * N);
         }
     }
-    free(X); free(Xa); free(Y); free(Ya); free(a);
+    free(X); free(Xa); free(Y); free(Ya); free(a); free(rho0);
     free(cls); free(p); free(tmp);
     return 0;
+}
+
+int orc_vacf(int nx, int ny, int nz, const uint8_t* solid, const double* u,
+             double lambda, double pa, double pd, int nbhd, long T, int qmask,
+             double* Z, double* V, double* mass, double* mom)
+{
+    return orc_vacf_charged(nx, ny, nz, solid, u, lambda, pa, pd, nbhd, NULL, T, qmask,
+                            Z, V, mass, mom);
 }
 
 /* ---- steady BGK flow (Eq. 6) -------------------------------------------- */

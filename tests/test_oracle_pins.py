@@ -431,3 +431,71 @@ def test_bgk_enclosed_node_has_zero_mean_velocity(orc):
     r = orc.bgk(m, 1.0, g, 1e-10, 1000)
     # |u(t)| = |g|/2 every step; the average cancels to rounding (1.5e-18 measured)
     assert np.abs(r["u"]).max() <= 1e-10 * np.abs(g).max()
+
+
+# ---------------------------------------------------------------- charged tracers
+# Sec. II: for charged tracers Eq. 8 carries a Q term set by gradients of the
+# excess chemical potential mu^ex = q psi, and Eq. 11 weights each node by
+# exp(-beta mu^ex). Reading: Q_i(r) = exp(-(beta mu^ex(r + c_i) - beta mu^ex(r))/2),
+# the symmetric factor under which the Eq. 11 weights satisfy detailed balance.
+def test_charged_vacf_equals_dense_chain(orc):
+    """Random porous lattice with flow, sorption and a random potential: the
+    propagated VACF equals pi0^T B M^(m-1) b of the explicit chain (Boltzmann
+    start, Q-scaled hops) built independently in numpy."""
+    m = inputs.random_mask(4, 4, 5, 0.3, seed=21)
+    u = inputs.random_velocity(m, 0.04, seed=22)
+    bmu = np.random.default_rng(23).uniform(-1.0, 1.0, m.shape)
+    r = orc.vacf(m, u, 1.0, 0.07, 0.03, 15, bmu=bmu)
+    Zc, Vc = chain.dense_chain_vacf(m, u, 1.0, 0.07, 0.03, 15, bmu=bmu)
+    assert np.abs(r["Z"] - Zc).max() <= 1e-12 * np.abs(Zc).max()
+    assert np.abs(r["V"] - Vc).max() <= 1e-15
+
+
+def test_charged_boltzmann_weights_stationary_at_rest(orc):
+    """At rest the Eq. 11 weights with exp(-beta mu^ex) (mobile, and times
+    k_a/k_d adsorbed) are a fixed point of Eqs. 7, 9, 10 with the Q term."""
+    m = inputs.random_mask(6, 5, 7, 0.3, seed=31)
+    bmu = np.random.default_rng(32).uniform(-1.5, 1.5, m.shape)
+    pa, pd = 0.05, 0.02
+    cls = orc.classify(m)
+    w = np.where(cls > 0, np.exp(-bmu), 0.0)
+    Z = w.sum() + (pa / pd) * w[cls == 2].sum()
+    X0 = w / Z
+    Xa0 = np.where(cls == 2, (pa / pd) * w / Z, 0.0)
+    X, Xa = orc.propagate(m, None, 0.8, pa, pd, 40, X0, Xa0, bmu=bmu)
+    assert np.abs(X - X0).max() <= 1e-13 * X0.max()      # rounding over 40 steps: 2e-15 measured
+    assert np.abs(Xa - Xa0).max() <= 1e-13 * Xa0.max()
+    # without the Q term the same start drifts: the pin is not trivial
+    Xn, _ = orc.propagate(m, None, 0.8, pa, pd, 40, X0, Xa0)
+    assert np.abs(Xn - X0).max() > 1e-3 * X0.max()
+
+
+def test_charged_periodic_potential_effective_diffusion(orc):
+    """Bulk lattice, potential periodic along z only: across the potential the
+    walk is a one-dimensional chain with hop probabilities (lambda/12) Q, whose
+    long-time diffusion coefficient is the textbook series-conductance
+    (Lifson-Jackson) result for detailed-balance hopping,
+    D = (lambda/12) / (<exp(-beta mu_z)> <exp((beta mu_z + beta mu_z+1)/2)>);
+    along x and y nothing changes with time and D_x = D_y."""
+    nz, lam = 8, 0.9
+    m = inputs.bulk_mask(3, 3, nz)
+    z = np.arange(nz)
+    mu = 1.2 * np.sin(2 * np.pi * z / nz) + 0.3 * np.cos(4 * np.pi * z / nz + 0.4)
+    bmu = np.broadcast_to(mu[:, None, None], m.shape).copy()
+    r = orc.vacf(m, None, lam, 0.0, 0.5, 800, bmu=bmu)
+    D = orc.d_of_t(r["Z"], r["V"])
+    lj = (lam / 12) / (np.mean(np.exp(-mu)) * np.mean(np.exp((mu + np.roll(mu, -1)) / 2)))
+    assert abs(D[2, -1] / lj - 1) < 1e-12          # 4e-16 measured
+    assert abs(D[2, 0] / lj - 1) > 0.1             # the potential slows it down over time
+    assert np.abs(D[0] - D[1]).max() == 0.0 and np.abs(D[0] - D[0, 0]).max() < 1e-16
+
+
+def test_uniform_potential_is_neutral(orc):
+    """A constant excess chemical potential changes nothing (Q = 1, and the
+    Boltzmann factor cancels in the normalisation)."""
+    m = inputs.random_mask(5, 4, 6, 0.25, seed=41)
+    u = inputs.random_velocity(m, 0.03, seed=42)
+    a = orc.vacf(m, u, 0.7, 0.04, 0.02, 30)
+    b = orc.vacf(m, u, 0.7, 0.04, 0.02, 30, bmu=np.full(m.shape, 0.8))
+    assert np.abs(a["Z"] - b["Z"]).max() <= 1e-14 * np.abs(a["Z"]).max()
+    assert np.abs(a["mass"] - b["mass"]).max() <= 1e-14
