@@ -176,6 +176,28 @@ lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* Z, 
 lbmp_status mp_steps_done(const lbmp_mp* h, int64_t* t);
 
 /*
+ * mp_init for charged tracers (Sec. II: the Q term of Eq. 8 and the excess
+ * chemical potential of Eq. 11, whose mean-field electrostatic part is q psi).
+ * beta_mu_ex[g]: host array of N doubles, the dimensionless excess chemical
+ * potential beta mu^ex(r) of the tracers of geometry g at every node (e.g. the
+ * valence times the reduced electrostatic potential), x fastest like the
+ * geometry; values on solid nodes are ignored; NULL for a neutral geometry.
+ * Every species of a geometry shares it (a flow may appear several times with
+ * different species sets and potentials). With it:
+ *  - p_i(r) = w_i (lambda Q_i(r)/2 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
+ *    Q_i(r) = exp(-(beta mu^ex(r + c_i) - beta mu^ex(r)) / 2), the symmetric
+ *    factor under which the Eq. 11 weights satisfy detailed balance at rest;
+ *  - Eq. 11 weights exp(-beta mu^ex(r)) / Z on fluid nodes, times
+ *    (1 + k_a / k_d) on interfacial nodes.
+ * Otherwise as mp_init (same workspace size); LBMP_EINVAL also for a
+ * non-finite beta_mu_ex at a fluid node, LBMP_EPROB when a Q factor makes a
+ * stay probability negative.
+ */
+lbmp_status mp_init_charged(const lbmp_flow* const* flows, const lbmp_species* species,
+                            const double* const* beta_mu_ex, int n_geom, int precision,
+                            int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                            lbmp_mp** out);
+/*
  * Out-of-equilibrium uptake (the outlook of the paper's conclusion: the
  * density as the propagated quantity of Eqs. 7, 9 and 10, irreversible
  * adsorption k_d = 0 allowed). Arguments as for mp_init, except that k_d may

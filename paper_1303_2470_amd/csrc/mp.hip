@@ -1312,10 +1312,12 @@ __global__ void __launch_bounds__(RED_T) k_mp_reduce(const GeomDev<T>* __restric
 
 
 // ------------------------------------------------------------------ set-up
-// Link probabilities of Eq. 8 (local equilibrium, Q = 1), FP64, per node and
-// link; zero on solid nodes and for links into solid nodes.
+// Link probabilities of Eq. 8 (local equilibrium), FP64, per node and link;
+// zero on solid nodes and for links into solid nodes. bmu (nullable): the
+// tracer's excess chemical potential beta mu^ex per node; the diffusive term
+// then carries Q = exp(-(bmu(r + c_i) - bmu(r)) / 2) (Q = 1 without it).
 __global__ void k_pout(const int8_t* __restrict__ cls, const double* __restrict__ u, int nx, int ny,
-                       int nz, double lam, double* __restrict__ pout) {
+                       int nz, double lam, const double* __restrict__ bmu, double* __restrict__ pout) {
     const int64_t N = (int64_t)nx * ny * nz;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -1328,7 +1330,8 @@ __global__ void k_pout(const int8_t* __restrict__ cls, const double* __restrict_
             int64_t m = modp(x + lcx(k), nx) + (int64_t)nx * (modp(y + lcy(k), ny) + (int64_t)ny * modp(z + lcz(k), nz));
             if (cls[m] != 0) {
                 double cu = lcx(k) * ux + lcy(k) * uy + lcz(k) * uz;
-                p = lw(k) * (0.5 * lam + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                const double Q = bmu ? exp(-0.5 * (bmu[m] - bmu[n])) : 1.0;
+                p = lw(k) * (0.5 * lam * Q + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
             }
         }
         pout[(int64_t)k * N + n] = p;
@@ -1338,13 +1341,15 @@ __global__ void k_pout(const int8_t* __restrict__ cls, const double* __restrict_
 // Stored tables and per-node set-up values. Sums of stored (rounded) link
 // probabilities are formed in FP64, so sigma and src describe exactly the
 // chain the stored table propagates.
-// setup partials per block: [0..2] sum_r a_g, [3..5] sum_r sum_i p_i c_ig^2,
+// w (nullable): relative Eq. 11 weight exp(-beta mu^ex) of every node (1
+// without an excess chemical potential); sums over r below are weighted by it.
+// setup partials per block: [0..2] sum_r w a_g, [3..5] sum_r w sum_i p_i c_ig^2,
 // [6] min p_i, [7] max |u|, [8] min stay (bulk), [9] min stay (interface),
-// [10] number of fluid nodes, [11] unused.
+// [10] sum of w over fluid nodes, [11] sum of w over interfacial nodes.
 template <typename T>
 __global__ void k_links(const int8_t* __restrict__ cls, const double* __restrict__ pout,
-                        const double* __restrict__ u, int nx, int ny, int nz, T* __restrict__ pin,
-                        double* __restrict__ sig, T* __restrict__ src, T* __restrict__ a,
+                        const double* __restrict__ u, int nx, int ny, int nz, const double* __restrict__ w,
+                        T* __restrict__ pin, double* __restrict__ sig, T* __restrict__ src, T* __restrict__ a,
                         double* __restrict__ b64, double* __restrict__ src64,
                         double* __restrict__ part) {
     __shared__ double lds[SETUP_RED * BLK];
@@ -1367,16 +1372,18 @@ __global__ void k_links(const int8_t* __restrict__ cls, const double* __restrict
             int64_t m = modp(x - lcx(k), nx) + (int64_t)nx * (modp(y - lcy(k), ny) + (int64_t)ny * modp(z - lcz(k), nz));
             const T pt = fl ? (T)pout[(int64_t)k * N + m] : T(0);
             pin[(int64_t)k * N + n] = pt;
-            sin += (double)pt;
-            bg[0] += (double)pt * lcx(k);
-            bg[1] += (double)pt * lcy(k);
-            bg[2] += (double)pt * lcz(k);
+            const double wpt = (w ? w[m] : 1.0) * (double)pt;  // weighted arrival from r - c_k
+            sin += wpt;
+            bg[0] += wpt * lcx(k);
+            bg[1] += wpt * lcy(k);
+            bg[2] += wpt * lcz(k);
             if (fl && cls[m] != 0) v[6] = fmin(v[6], pout[(int64_t)k * N + n]);
         }
         sig[n] = fl ? sout : 0.0;
-        // arrivals minus departures of the stored table, both summed exactly:
-        // zero wherever the Eq. 11 weights are stationary for that table
-        const double s64 = fl ? sin - sout : 0.0;
+        // weighted arrivals minus departures of the stored table, both summed
+        // exactly: zero wherever the Eq. 11 weights are stationary for that table
+        const double wn = w ? w[n] : 1.0;
+        const double s64 = fl ? sin - wn * sout : 0.0;
         src[n] = (T)s64;
         src64[n] = s64;
         for (int g = 0; g < 3; ++g) {
@@ -1385,13 +1392,14 @@ __global__ void k_links(const int8_t* __restrict__ cls, const double* __restrict
         }
         if (fl) {
             for (int g = 0; g < 3; ++g) {
-                v[g] = ag[g];
-                v[3 + g] = c2[g];
+                v[g] = wn * ag[g];
+                v[3 + g] = wn * c2[g];
             }
             const double uu = sqrt(u[n] * u[n] + u[N + n] * u[N + n] + u[2 * N + n] * u[2 * N + n]);
             v[7] = uu;
             if (cls[n] == 2) v[9] = 1.0 - sout; else v[8] = 1.0 - sout;
-            v[10] = 1.0;
+            v[10] = wn;
+            v[11] = cls[n] == 2 ? wn : 0.0;
         }
     }
     const int tid = threadIdx.x;
@@ -1423,13 +1431,14 @@ __global__ void k_setup_final(const double* __restrict__ part, int nb, double* _
 }
 
 // State at t = 1 (deviations): density rho_ref*src; first moments
-// rho_ref*(b_q - V_q); adsorbed density 0; adsorbed first moments -V_q Gamma_ref.
+// rho_ref*(b_q - V_q w); adsorbed density 0; adsorbed first moments
+// -V_q Gamma_ref w (w the relative Eq. 11 weight of the node, 1 when null).
 template <typename T>
 __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __restrict__ ilist,
                              int64_t N, int64_t NI, int S, const double* __restrict__ spc,
                              const double* __restrict__ b64, const double* __restrict__ src64,
-                             const int32_t* __restrict__ fidx, int64_t NC, T* __restrict__ X,
-                             T* __restrict__ Xa) {
+                             const double* __restrict__ w, const int32_t* __restrict__ fidx, int64_t NC,
+                             T* __restrict__ X, T* __restrict__ Xa) {
     // spc per species: rho_ref, Gamma_ref, V0, V1, V2; fields dense (fidx
     // null, NC = N) or compact (node n at fidx[n], solid nodes not stored)
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1438,13 +1447,16 @@ __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __re
     if (n < N && (!fidx || fidx[n] >= 0)) {
         const bool fl = cls[n] != 0;
         const int64_t i = fidx ? fidx[n] : n;
+        const double wn = w ? w[n] : 1.0;
         X[(int64_t)(4 * s) * NC + i] = fl ? (T)(rr * src64[n]) : T(0);
         for (int q = 1; q < 4; ++q)
-            X[(int64_t)(4 * s + q) * NC + i] = fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q]) : T(0);
+            X[(int64_t)(4 * s + q) * NC + i] =
+                fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q] * wn) : T(0);
     }
     if (n < NI) {
+        const double wn = w ? w[ilist[n]] : 1.0;
         Xa[(int64_t)(4 * s) * NI + n] = T(0);
-        for (int q = 1; q < 4; ++q) Xa[(int64_t)(4 * s + q) * NI + n] = (T)(-spc[5 * s + 1 + q] * gr);
+        for (int q = 1; q < 4; ++q) Xa[(int64_t)(4 * s + q) * NI + n] = (T)(-spc[5 * s + 1 + q] * gr * wn);
     }
 }
 
@@ -1508,6 +1520,11 @@ struct GeomHost {
     double A[3], B[3];
     double min_p, max_u, min_stay_bulk, min_stay_iface, pa_max;
     std::vector<double> V, Z0;  // [S][3]
+    // charged tracers: beta mu^ex per node (empty: neutral) and the relative
+    // Eq. 11 weights exp(-(beta mu^ex - its minimum over fluid nodes)); the
+    // weighted fluid and interfacial totals (N_F and N_I when neutral)
+    std::vector<double> bmu, w;
+    double sumw_f = 0.0, sumw_i = 0.0;
     int64_t ntile_max;
     // device buffers
     void *pin, *sig, *src, *a, *X0, *X1, *Xa, *coef, *prob;
@@ -1554,7 +1571,11 @@ int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     return (((int64_t)f->nx * f->ny + BLK - 1) / BLK) * zb;
 }
 
-int64_t setup_doubles(int64_t N) { return 22 * N + ((N + BLK - 1) / BLK) * SETUP_RED + SETUP_RED; }
+// set-up scratch: pout 18 N | b64 3 N | src64 N | block partials | final sums |
+// bmu N | w N (the last two survive the compaction of the link tables, which
+// reuses the head of the region)
+int64_t setup_doubles(int64_t N) { return 24 * N + ((N + BLK - 1) / BLK) * SETUP_RED + SETUP_RED; }
+double* setup_bmu(double* base, int64_t N) { return base + 22 * N + ((N + BLK - 1) / BLK) * SETUP_RED + SETUP_RED; }
 
 template <typename T>
 void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
@@ -1895,8 +1916,16 @@ lbmp_status build_links(lbmp_mp* h, GeomHost& g, hipStream_t s, double* fin_host
     double* part = src64 + N;
     const unsigned nb = (unsigned)((N + BLK - 1) / BLK);
     double* fin = part + (size_t)nb * SETUP_RED;
-    k_pout<<<nb, BLK, 0, s>>>(f->d.cls, f->d.u, f->nx, f->ny, f->nz, g.lam, pout);
-    k_links<T><<<nb, BLK, 0, s>>>(f->d.cls, pout, f->d.u, f->nx, f->ny, f->nz, (T*)g.pin, (double*)g.sig,
+    double* bmu = nullptr;
+    double* w = nullptr;
+    if (!g.bmu.empty()) {
+        bmu = setup_bmu(h->setup_tmp, N);
+        w = bmu + N;
+        LBMP_HIP(hipMemcpyAsync(bmu, g.bmu.data(), N * 8, hipMemcpyHostToDevice, s));
+        LBMP_HIP(hipMemcpyAsync(w, g.w.data(), N * 8, hipMemcpyHostToDevice, s));
+    }
+    k_pout<<<nb, BLK, 0, s>>>(f->d.cls, f->d.u, f->nx, f->ny, f->nz, g.lam, bmu, pout);
+    k_links<T><<<nb, BLK, 0, s>>>(f->d.cls, pout, f->d.u, f->nx, f->ny, f->nz, w, (T*)g.pin, (double*)g.sig,
                                   (T*)g.src, (T*)g.a, b64, src64, part);
     k_setup_final<<<1, 64, 0, s>>>(part, nb, fin);
     LBMP_HIP(hipGetLastError());
@@ -1919,6 +1948,8 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     g.max_u = r[7];
     g.min_stay_bulk = r[8];
     g.min_stay_iface = r[9];
+    g.sumw_f = r[10];  // sums of 1 over the fluid and interfacial nodes when neutral: N_F, N_I exactly
+    g.sumw_i = r[11];
     std::vector<double> spc(S * 5), spc0(S * 7, 0.0);
     std::vector<T> coef(S * 4), prob(S * 2);
     std::vector<double> kc(S * KC, 0.0);
@@ -1930,7 +1961,7 @@ lbmp_status species_constants(lbmp_mp* h, GeomHost& g, const double* r, hipStrea
     for (int sp = 0; sp < S; ++sp) {
         // uptake mode stores absolute densities (no reference, no source)
         const double Kr = h->uptake ? 0.0 : g.pa[sp] / g.pd[sp];
-        const double Zp = (double)g.nf + (double)g.NI * Kr;
+        const double Zp = g.sumw_f + g.sumw_i * Kr;
         const double rr = h->uptake ? 0.0 : 1.0 / Zp, gr = Kr / Zp;
         g.rho_ref[sp] = rr;
         g.gam_ref[sp] = gr;
@@ -2035,7 +2066,8 @@ lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
         return LBMP_OK;
     }
     dim3 grid((unsigned)((std::max<int64_t>(N, g.NI) + BLK - 1) / BLK), (unsigned)g.S);
-    k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64,
+    const double* w = g.bmu.empty() ? nullptr : setup_bmu(h->setup_tmp, N) + N;
+    k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64, w,
                                          compact_fields(h) ? g.fidx : nullptr, compact_fields(h) ? g.nf : N,
                                          (T*)g.X1, (T*)g.Xa);
     LBMP_HIP(hipGetLastError());
@@ -2119,9 +2151,12 @@ extern "C" lbmp_status mp_workspace_bytes(const lbmp_flow* const* flows, const l
 }
 
 namespace {
-lbmp_status mp_create(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom, int precision,
-                      int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes, void* hip_stream, bool uptake,
-                      lbmp_mp** out) {
+// beta_mu_ex (nullable, and per geometry nullable): excess chemical potential
+// of the tracers of a geometry, beta mu^ex per node (host, N doubles; values
+// on solid nodes are ignored).
+lbmp_status mp_create(const lbmp_flow* const* flows, const lbmp_species* species, const double* const* beta_mu_ex,
+                      int n_geom, int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
+                      void* hip_stream, bool uptake, lbmp_mp** out) {
     if (!out) return fail(LBMP_EINVAL, "out is NULL");
     *out = nullptr;
     size_t need = 0;
@@ -2140,6 +2175,34 @@ lbmp_status mp_create(const lbmp_flow* const* flows, const lbmp_species* species
         resolve_lambda(species[gi], &g.lam);
         g.pa.assign(species[gi].k_a, species[gi].k_a + g.S);  // p_a = k_a dt / dx
         g.pd.assign(species[gi].k_d, species[gi].k_d + g.S);  // p_d = k_d dt
+        if (beta_mu_ex && beta_mu_ex[gi]) {
+            const double* b = beta_mu_ex[gi];
+            std::vector<int8_t> cls(g.N);
+            hipError_t e = hipMemcpy(cls.data(), g.flow->d.cls, g.N, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                delete h;
+                return fail(LBMP_EDEVICE, "hipMemcpy of the node classes failed: %s", hipGetErrorString(e));
+            }
+            double bmin = INFINITY;
+            for (int64_t n = 0; n < g.N; ++n) {
+                if (!cls[n]) continue;
+                if (!std::isfinite(b[n])) {
+                    delete h;
+                    return fail(LBMP_EINVAL, "geometry %d: beta_mu_ex is not finite at fluid node %lld", gi,
+                                (long long)n);
+                }
+                bmin = std::min(bmin, b[n]);
+            }
+            // relative weights exp(-(beta mu^ex - min)): at most 1, the
+            // normalisation absorbs the shift
+            g.bmu.assign(g.N, 0.0);
+            g.w.assign(g.N, 0.0);
+            for (int64_t n = 0; n < g.N; ++n)
+                if (cls[n]) {
+                    g.bmu[n] = b[n];
+                    g.w[n] = std::exp(-(b[n] - bmin));
+                }
+        }
     }
     Carver c(dev_ws, ws_bytes);
     carve_all(h, c);
@@ -2160,15 +2223,24 @@ lbmp_status mp_create(const lbmp_flow* const* flows, const lbmp_species* species
 extern "C" lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
                                int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
                                void* hip_stream, lbmp_mp** out) {
-    return mp_create(flows, species, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream, false,
-                     out);
+    return mp_create(flows, species, nullptr, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream,
+                     false, out);
+}
+
+extern "C" lbmp_status mp_init_charged(const lbmp_flow* const* flows, const lbmp_species* species,
+                                       const double* const* beta_mu_ex, int n_geom, int precision,
+                                       int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                                       lbmp_mp** out) {
+    if (!beta_mu_ex) return fail(LBMP_EINVAL, "beta_mu_ex is NULL (use mp_init for neutral tracers)");
+    return mp_create(flows, species, beta_mu_ex, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes,
+                     hip_stream, false, out);
 }
 
 extern "C" lbmp_status mp_uptake_init(const lbmp_flow* const* flows, const lbmp_species* species, int n_geom,
                                       int precision, int64_t max_steps_recorded, void* dev_ws, size_t ws_bytes,
                                       void* hip_stream, lbmp_mp** out) {
-    return mp_create(flows, species, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream, true,
-                     out);
+    return mp_create(flows, species, nullptr, n_geom, precision, max_steps_recorded, dev_ws, ws_bytes, hip_stream,
+                     true, out);
 }
 
 extern "C" lbmp_status mp_uptake(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* mobile,
@@ -2266,8 +2338,8 @@ extern "C" lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, 
     LBMP_HIP(hipStreamSynchronize(s));
     if (mass)
         for (int sp = 0; sp < S; ++sp) {
-            mass[2 * sp] = g.rho_ref[sp] * (double)g.nf + (last.empty() ? 0.0 : last[sp * NRED + 3]);
-            mass[2 * sp + 1] = g.gam_ref[sp] * (double)g.NI + (last.empty() ? 0.0 : last[sp * NRED + 7]);
+            mass[2 * sp] = g.rho_ref[sp] * g.sumw_f + (last.empty() ? 0.0 : last[sp * NRED + 3]);
+            mass[2 * sp + 1] = g.gam_ref[sp] * g.sumw_i + (last.empty() ? 0.0 : last[sp * NRED + 7]);
         }
     if (vbar)
         for (int i = 0; i < 3 * S; ++i) vbar[i] = g.V[i];
@@ -2330,12 +2402,14 @@ extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, do
         const double cq = q == 0 ? 1.0 : g.V[3 * species + q - 1];
         int64_t i = 0;  // index among the fluid nodes
         for (int64_t n = 0; n < N; ++n) {
-            if (X) X[q * N + n] = cls[n] ? at(hx, q * NC + (NC == N ? n : i)) + cq * rr : 0.0;
+            const double wn = g.w.empty() ? 1.0 : g.w[n];
+            if (X) X[q * N + n] = cls[n] ? at(hx, q * NC + (NC == N ? n : i)) + cq * rr * wn : 0.0;
             if (cls[n]) ++i;
         }
         if (Xads) {
             for (int64_t n = 0; n < N; ++n) Xads[q * N + n] = 0.0;
-            for (int64_t i = 0; i < NI; ++i) Xads[q * N + ilist[i]] = at(ha, q * NIa + i) + cq * gr;
+            for (int64_t i = 0; i < NI; ++i)
+                Xads[q * N + ilist[i]] = at(ha, q * NIa + i) + cq * gr * (g.w.empty() ? 1.0 : g.w[ilist[i]]);
         }
     }
     return LBMP_OK;

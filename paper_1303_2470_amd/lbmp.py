@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["lbmp_last_error", "lbmp_version", "lb_flow_workspace_bytes", "lb_flow_solve",
            "lb_flow_solve_static", "lb_flow_static_max_nodes", "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
-           "mp_workspace_bytes", "mp_init", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
+           "mp_workspace_bytes", "mp_init", "mp_init_charged", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
            "mp_uptake_init", "mp_uptake",
            "mp_state", "mp_profile_steps", "mp_free", "sg_param_count", "sg_workspace_bytes",
            "sg_create", "sg_set_params", "sg_get_params", "sg_set_normalization", "sg_train_step",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "lb_flow_free": ([vp], None),
         "mp_workspace_bytes": ([P(vp), P(Species), i32, i32, i64, P(sz)], i32),
         "mp_init": ([P(vp), P(Species), i32, i32, i64, vp, sz, vp, P(vp)], i32),
+        "mp_init_charged": ([P(vp), P(Species), P(vp), i32, i32, i64, vp, sz, vp, P(vp)], i32),
         "mp_step_n": ([vp, i64], i32),
         "mp_vacf": ([vp, i32, i64, i64, vp, vp, vp, vp], i32),
         "mp_uptake_init": ([P(vp), P(Species), i32, i32, i64, vp, sz, vp, P(vp)], i32),
@@ -308,8 +309,10 @@ class MP:
 
 
 def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stream=None,
-            _entry: str = "mp_init") -> MP:
-    """Set up moment propagation for flows[g] with species[g] = dict(D_b= or Delta=, k_a=, k_d=)."""
+            _entry: str = "mp_init", beta_mu_ex=None) -> MP:
+    """Set up moment propagation for flows[g] with species[g] = dict(D_b= or Delta=, k_a=, k_d=).
+    beta_mu_ex: for charged tracers, one (nz, ny, nx) array (or None) per geometry
+    (C-ABI mp_init_charged)."""
     torch = _torch_cuda()
     load_library()
     if isinstance(flows, Flow):
@@ -332,8 +335,27 @@ def mp_init(flows, species, precision: int = LBMP_FP32, max_steps: int = 0, stre
     stream = stream or torch.cuda.Stream()
     _enter(stream, ws)
     h = ctypes.c_void_p()
-    _check(getattr(_lib, _entry)(fl, sps, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()), nb.value,
-                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+    if beta_mu_ex is not None:
+        if isinstance(beta_mu_ex, np.ndarray):
+            beta_mu_ex = [beta_mu_ex]
+        if len(beta_mu_ex) != n:
+            raise ValueError("one beta_mu_ex array (or None) per flow")
+        arrs = []
+        for f, b in zip(flows, beta_mu_ex):
+            if b is None:
+                arrs.append(None)
+                continue
+            a = np.ascontiguousarray(b, dtype=np.float64)
+            if a.shape != f.shape:
+                raise ValueError("beta_mu_ex must have the geometry's (nz, ny, nx) shape")
+            arrs.append(a)
+        keep.append(arrs)
+        bp = (ctypes.c_void_p * n)(*[None if a is None else a.ctypes.data for a in arrs])
+        _check(_lib.mp_init_charged(fl, sps, bp, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()),
+                                    nb.value, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+    else:
+        _check(getattr(_lib, _entry)(fl, sps, n, precision, max_steps, ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
     return MP(h, ws, list(flows), [int(s.n_species) for s in sps], stream, keep)
 
 
