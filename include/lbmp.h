@@ -159,6 +159,12 @@ lbmp_status mp_init(const lbmp_flow* const* flows, const lbmp_species* species, 
  * LBMP_ESTATE if the total would exceed max_steps_recorded.
  */
 lbmp_status mp_step_n(lbmp_mp* h, int64_t n_steps);
+/* Device watchdog of the step: after every step the total probability
+ * (mobile + adsorbed) of every species must stay within LBMP_MASS_DRIFT_MAX
+ * of 1 and be finite; otherwise mp_vacf and mp_uptake return LBMP_ENUMERIC
+ * naming the first step where it did not. The environment variable
+ * LBMP_MASS_DRIFT_MAX, read by mp_init, overrides the threshold. */
+#define LBMP_MASS_DRIFT_MAX 1e-6
 /*
  * Synchronises the stream and returns, for geometry `geom`, times
  * t = t0 .. t0+count-1 (t <= steps done; t = 0 is the start):
@@ -168,7 +174,7 @@ lbmp_status mp_step_n(lbmp_mp* h, int64_t n_steps);
  *  mass[s*2 + {0,1}]     total mobile and adsorbed probability at the last t;
  *  vbar[s*3 + g]         mean velocity V_g.
  * Any output pointer may be NULL. LBMP_ENUMERIC if a recorded value is not
- * finite.
+ * finite or the watchdog (LBMP_MASS_DRIFT_MAX) fired.
  */
 lbmp_status mp_vacf(lbmp_mp* h, int geom, int64_t t0, int64_t count, double* Z, double* D,
                     double* mass, double* vbar);
