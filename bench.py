@@ -91,7 +91,7 @@ def traffic_record(key: str):
 KERNELS = {0: ("direct", "k_mp_step"), 1: ("lds-box", "k_mp_step_box"), 2: ("z-march", "k_mp_march"),
            3: ("lds-dma", "k_mp_dma"), 4: ("lds-dma-zpair", "k_mp_dma"),
            5: ("lds-dma-rows", "k_mp_dma"), 6: ("lds-dma-zpair-rows", "k_mp_dma"),
-           7: ("lds-dma-zpair-lanes", "k_mp_dma")}
+           7: ("lds-dma-zpair-lanes", "k_mp_dma"), 8: ("gathered-chunks", "k_mp_gather")}
 
 
 def rocprof_summary(root: str) -> dict:
@@ -130,13 +130,14 @@ def traffic_from_counters(root: str, copy_bytes: int) -> dict:
     def pick(name_part, counter):
         vals = [v[counter]["median"] for k, v in summ.items() if name_part in k and counter in v]
         return vals[0] if vals else None
-    fk, wk = pick("k_mp_dma", "FETCH_SIZE"), pick("k_mp_dma", "WRITE_SIZE")
+    kern = os.environ.get("LBMP_KERNEL", "k_mp_dma")
+    fk, wk = pick(kern, "FETCH_SIZE"), pick(kern, "WRITE_SIZE")
     # the copy kernel: the only other kernel profiled in those runs
     cf = [v["FETCH_SIZE"]["median"] for k, v in summ.items() if "k_mp" not in k and "FETCH_SIZE" in v]
     cw = [v["WRITE_SIZE"]["median"] for k, v in summ.items() if "k_mp" not in k and "WRITE_SIZE" in v]
     f_scale = copy_bytes / (max(cf) * 1024.0)
     w_scale = copy_bytes / (max(cw) * 1024.0)
-    return {"kernel": "k_mp_dma", "tile": os.environ.get("LBMP_TILE"),
+    return {"kernel": kern, "tile": os.environ.get("LBMP_TILE"),
             "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
             "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
             "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale}

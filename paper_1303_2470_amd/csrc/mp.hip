@@ -66,6 +66,16 @@ struct GeomDev {
     // null, NC = N
     const int32_t* fidx;
     int64_t NC;
+    // gathered chunks (variant 8): chunk c covers compact nodes
+    // gch[c].x .. gch[c].x + gch[c].y - 1 (one per thread) and the halo
+    // ghsrc[gch[c].z .. + gch[c].w - 1]; node i's lattice index gnode[i], its
+    // adsorbed-field index gaslot[i] (-1 off the interface) and, per link k,
+    // the region slot of r - c_k in gnbr[k * NC + i]
+    const int4* gch;
+    const int32_t* ghsrc;
+    const int32_t* gnode;
+    const int32_t* gaslot;
+    const uint16_t* gnbr;
     const T* coef;             // [S][4]
     const T* prob;             // [S][2] = p_a, p_d
     const double* kc;          // [S][KC]: p_a, p_d, c_0..c_3 (coef), -V_0..-V_2, FP64
@@ -1225,6 +1235,257 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     finish(pend);
 }
 
+
+// ------------------------------------------------------------------ gathered chunks
+// Variant 8: a block updates one chunk of up to GCH fluid nodes that are
+// consecutive in the compact storage, whose order (tiles of 8 x 8 x 8 lattice
+// nodes, fluid nodes in lattice order within a tile) keeps a chunk spatially
+// compact. Per field the buffer unit copies the chunk's own values (one
+// contiguous range) and those of its halo (the fluid nodes outside the chunk
+// that its nodes pull from, a precomputed list of compact indices) into an
+// LDS region; each thread then reads its 18 arrivals at precomputed region
+// slots (links from solid nodes read a slot the copy leaves at zero). Every
+// thread has a fluid node, whatever the porosity, and only fluid values are
+// copied. The arithmetic, its order and the rounding bits are those of the
+// LDS-DMA blocks, so the stored fields are bitwise the same.
+constexpr int GCH = 2 * BLK;                     // nodes per chunk, threads per block
+constexpr int GRLD = 3;                          // region copies per thread and field
+constexpr int GREG = GRLD * GCH;                 // region slots: chunk, halo, zeros
+constexpr int GZSLOT = GREG - 1;                 // never filled: reads 0
+constexpr int GTILE = 8;                         // edge of the ordering tiles
+
+__global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k_mp_gather(
+    const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
+    constexpr int DBLK = GCH, RLD = GRLD, NCP = GRLD, REGION = GREG, STAGE = GREG + GCH;
+    constexpr int NW = DBLK / 64;
+    constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2, WAIT_IDLE = 2 * NCP;
+    __shared__ __align__(16) float st0[STAGE];
+    __shared__ __align__(16) float st1[STAGE];
+    __shared__ __align__(16) float st2[STAGE];
+    __shared__ __align__(16) float st3[STAGE];
+    __shared__ __align__(16) double rl[NSUM * DBLK];
+    __shared__ __align__(16) double l2[2 * NRED * 64];
+    float* const tag = nullptr;
+    const int64_t lb = xcd_remap(blockIdx.x, nblocks);
+    const int gi = find_geom(geoms, ngeom, lb);
+    const GeomDev<float>& G = geoms[gi];
+    const int64_t local = lb - G.blk0;
+    const int grp = (int)(local % G.ngrp);
+    const int64_t chunk = local / G.ngrp;
+    const int4 ch = G.gch[chunk];
+    const int cbase = ch.x, C = ch.y, hoff = ch.z, H = ch.w;
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int hf = wv >> 2, w4 = wv & 3;
+    const int64_t tile = 2 * chunk + hf;          // reduction tiles: the two halves of the chunk
+    const int NI = (int)G.NI, S = G.S;
+    const int NC = (int)G.NC;
+    const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
+    const int64_t ntile = G.ntile;
+    double* const part = G.part;
+    const bool act = tid < C;
+    const bool idle = __builtin_amdgcn_readfirstlane(wv * 64 >= C ? 1 : 0) != 0;
+    const int i = cbase + (act ? tid : 0);        // compact index of the node
+    const int n = act ? G.gnode[i] : 0;           // its lattice index
+    const int sl = act ? G.gaslot[i] : -1;
+    const bool isI = sl >= 0;
+    const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;
+    const int offa = isI ? sl * 4 : OOB;
+    const int offn = act ? i * 4 : OOB;
+    // region slot e = j * DBLK + tid: chunk node e, halo entry e - C, or nothing
+    int voff[NCP];
+#pragma unroll
+    for (int j = 0; j < NCP; ++j) {
+        const int e = j * DBLK + tid;
+        voff[j] = e < C ? (cbase + e) * 4 : (e < C + H ? G.ghsrc[hoff + e - C] * 4 : OOB);
+    }
+    // byte offsets of the 18 arrivals in the region
+    int nba[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) nba[k] = act ? 4 * (int)G.gnbr[(int64_t)k * NC + i] : 4 * GZSLOT;
+    double pin[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * G.N, (int64_t)G.N * 4), offn);
+    const double sig = __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, G.N * 8), act ? offn * 2 : OOB, 0, 0));
+    const double src = (double)bload(tag, mkrsrc(G.src, G.N * 4), offn);
+    float av[3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) av[g] = bload(tag, mkrsrc(G.a + (int64_t)g * G.N, G.N * 4), offn);
+    const double actd = act ? 1.0 : 0.0;
+    double avd[3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) avd[g] = act ? (double)av[g] : 0.0;
+    const int64_t t = ctl->t;
+    const uint32_t rbase = hash32((uint32_t)n * 0x9e3779b9u ^ hash32((uint32_t)t ^ ((uint32_t)gi << 24)));
+    const float* const Xin = (t & 1) ? G.X1 : G.X0;
+    float* const Xout = (t & 1) ? G.X0 : G.X1;
+    float* const Xa = G.Xa;
+    const __attribute__((address_space(4))) double* const kc =
+        (const __attribute__((address_space(4))) double*)G.kc;
+    const Stages stg{{st0, st1, st2, st3}};
+    const int NB = NC * 4, NIB = NI * 4;
+    const int64_t sN = 4 * (int64_t)NC, sNI = 4 * (int64_t)NI;
+    constexpr int GJ = 4096 / (DBLK * 4);
+    int vo[NCP];
+#pragma unroll
+    for (int j = 0; j < NCP; ++j) vo[j] = voff[j] == OOB ? OOB : voff[j] + 4096 - (j % GJ) * DBLK * 4;
+    const int voa = offa == OOB ? OOB : offa + 4096 - (RLD % GJ) * DBLK * 4;
+    auto issue = [&](auto qpc, auto anyc, const float* ib, const float* iab) {
+        constexpr int qp = decltype(qpc)::value;
+        const auto rin = mkrsrc(reinterpret_cast<const char*>(ib) - 4096, 4 * (int64_t)NB + 4096);
+        float* dst = stg.at<qp>() + wv * 64;
+        auto copy = [&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + (j / GJ) * GJ * DBLK), 4, vo[j], qp * NB,
+                                                     (j % GJ) * DBLK * 4, 0);
+        };
+        static_assert(NCP == 3, "three region copies per field");
+        copy(std::integral_constant<int, 0>());
+        copy(std::integral_constant<int, 1>());
+        copy(std::integral_constant<int, 2>());
+        if constexpr (decltype(anyc)::value) {
+            const auto rina = mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa,
+                                                     qp * NIB, (RLD % GJ) * DBLK * 4, 0);
+        }
+    };
+    const int ln = tid & 63;
+    auto fold = [&]() {
+        const double* p = rl + w4 * DBLK + hf * BLK + ln * 4;
+        const double* p4 = rl + 4 * DBLK + wv * 64 + (ln & 15) * 4;
+        using d2 = double __attribute__((ext_vector_type(2)));
+        d2 v;
+        v.x = ((p[0] + p[1]) + p[2]) + p[3];
+        v.y = ((p4[0] + p4[1]) + p4[2]) + p4[3];
+        *reinterpret_cast<d2*>(l2 + hf * (NRED * 64) + 2 * (w4 * 64 + ln)) = v;
+    };
+    auto finish = [&](int s) {
+        const int k = 2 * w4 + (ln >> 5), j = ln & 31;
+        const int i0 = k < 4 ? 2 * (k * 64 + 2 * j) : 2 * ((j >> 3) * 64 + ((2 * j) & 15)) + 1;
+        const double* l2h = l2 + hf * (NRED * 64);
+        double v = l2h[i0] + l2h[i0 + 2];
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        v += dpp_f64<0x124>(v);
+        v += dpp_f64<0x128>(v);
+        v += dpp_bcast15(v);
+        if (k >= 4 && k < 7) v = 0.0;
+        bstore(v, mkrsrc(part + (int64_t)max(s, 0) * ntile * NRED, ntile * NRED * 8),
+               (j == 31 && s >= 0) ? (int)(tile * NRED + k) * 8 : OOB);
+    };
+    int pend = -1, pend2 = -1;
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    auto run = [&](auto anyc, auto idlec) {
+        constexpr bool ANYI = decltype(anyc)::value;
+        constexpr bool IDLE = decltype(idlec)::value;
+        static_assert(!(IDLE && ANYI), "an idle wave has no interface node");
+        const float* in_s = Xin + (int64_t)s0 * sN;
+        const float* ina_s = Xa + (int64_t)s0 * sNI;
+        float* out_s = Xout + (int64_t)s0 * sN;
+        float* outa_s = Xa + (int64_t)s0 * sNI;
+        issue(std::integral_constant<int, 0>(), anyc, in_s, ina_s);
+        issue(std::integral_constant<int, 1>(), anyc, in_s, ina_s);
+        issue(std::integral_constant<int, 2>(), anyc, in_s, ina_s);
+        auto species = [&](int s, auto firstc, auto lastc) {
+            constexpr bool FIRST = decltype(firstc)::value, LAST = decltype(lastc)::value;
+            const float* const in_n = in_s + sN;
+            const float* const ina_n = ina_s + sNI;
+            const auto rout = mkrsrc(out_s, 4 * (int64_t)NB);
+            const auto rads = mkrsrc(outa_s, 4 * (int64_t)NIB);
+            const double pa = kc[KC * s], pd = kc[KC * s + 1];
+            double cq[4], w[3], nv[3];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cq[q] = kc[KC * s + 2 + q];
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                nv[g] = kc[KC * s + 6 + g];
+                w[g] = __builtin_fma(actd, nv[g], avd[g]);
+            }
+            double red[NSUM];
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) red[k] = 0.0;
+            auto field = [&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const int f = 4 * s + q;
+                if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
+                else if constexpr (IDLE) barrier_vm<WAIT_IDLE>();
+                else if constexpr (ANYI) barrier_vm<WAIT_I>();
+                else barrier_vm<WAIT_N>();
+                if constexpr (q == 0) {
+                    finish(pend2);
+                    pend2 = -1;
+                }
+                if constexpr (q == 1) {
+                    fold();
+                    pend2 = pend;
+                    pend = -1;
+                }
+                if constexpr (!IDLE) {
+                    using lvc = const volatile __attribute__((address_space(3))) char;
+                    lvc* const sb = (lvc*)stg.at<q>();
+                    float v[NL];
+                    const float c0 = *(const volatile __attribute__((address_space(3))) float*)(sb + 4 * tid);
+#pragma unroll
+                    for (int k = 0; k < NL; ++k)
+                        v[k] = *(const volatile __attribute__((address_space(3))) float*)(sb + nba[k]);
+                    const double xc = (double)c0;
+                    double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
+                    acc0 = __builtin_fma(cq[q], src, acc0);
+#pragma unroll
+                    for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
+                        if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
+                        else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
+                    }
+                    double nvx = acc0 + acc1;
+                    const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
+                    if constexpr (q == 0) red[3] += act ? xc : 0.0;
+                    else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
+                    if constexpr (ANYI) {  // sorption (Eqs. 9, 10)
+                        const double xa = (double)stg.at<q>()[REGION + tid];
+                        const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
+                        nvx = (nvx - fa) + fd;
+                        bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
+                        if constexpr (q == 0) red[4] += xa;
+                        else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
+                    }
+                    bstore(sround(nvx, r), rout, offn, q * NB);
+                }
+                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
+                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
+            };
+            field(std::integral_constant<int, 0>());
+            field(std::integral_constant<int, 1>());
+            field(std::integral_constant<int, 2>());
+            field(std::integral_constant<int, 3>());
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) rl[k * DBLK + tid] = red[k];
+            pend = s;
+            in_s = in_n;
+            ina_s = ina_n;
+            out_s += sN;
+            outa_s += sNI;
+        };
+        if (s1 - s0 == 1) {
+            species(s0, T_(), T_());
+        } else {
+            species(s0, T_(), F_());
+            for (int s = s0 + 1; s < s1 - 1; ++s) species(s, F_(), F_());
+            species(s1 - 1, F_(), T_());
+        }
+    };
+    if (idle) run(F_(), T_());
+    else if (anyI) run(T_(), F_());
+    else run(F_(), F_());
+    barrier_vm0();
+    finish(pend2);
+    barrier_vm0();
+    fold();
+    barrier_vm0();
+    finish(pend);
+}
+
 // Lattices with many tiles: chunks of RCH tile partials of every
 // (geometry, species) summed by one block each, in a fixed order, into
 // chunk[work][chunk][NRED]; k_mp_reduce then adds the chunks.
@@ -1459,7 +1720,7 @@ __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __re
                              int64_t N, int64_t NI, int S, const double* __restrict__ spc,
                              const double* __restrict__ b64, const double* __restrict__ src64,
                              const double* __restrict__ w, const int32_t* __restrict__ fidx, int64_t NC,
-                             T* __restrict__ X, T* __restrict__ Xa) {
+                             const int32_t* __restrict__ aperm, T* __restrict__ X, T* __restrict__ Xa) {
     // spc per species: rho_ref, Gamma_ref, V0, V1, V2; fields dense (fidx
     // null, NC = N) or compact (node n at fidx[n], solid nodes not stored)
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1475,9 +1736,11 @@ __global__ void k_init_state(const int8_t* __restrict__ cls, const int32_t* __re
                 fl ? (T)(rr * b64[(int64_t)(q - 1) * N + n] - rr * spc[5 * s + 1 + q] * wn) : T(0);
     }
     if (n < NI) {
+        // interface slot n; its adsorbed fields at aperm[n] (variant 8) or n
         const double wn = w ? w[ilist[n]] : 1.0;
-        Xa[(int64_t)(4 * s) * NI + n] = T(0);
-        for (int q = 1; q < 4; ++q) Xa[(int64_t)(4 * s + q) * NI + n] = (T)(-spc[5 * s + 1 + q] * gr * wn);
+        const int64_t ia = aperm ? aperm[n] : n;
+        Xa[(int64_t)(4 * s) * NI + ia] = T(0);
+        for (int q = 1; q < 4; ++q) Xa[(int64_t)(4 * s + q) * NI + ia] = (T)(-spc[5 * s + 1 + q] * gr * wn);
     }
 }
 
@@ -1551,6 +1814,17 @@ struct GeomHost {
     void *pin, *sig, *src, *a, *X0, *X1, *Xa, *coef, *prob;
     double *part, *series, *spc, *spc0, *kc, *zout, *dout;
     int32_t* fidx;  // [N] index of a fluid node among the fluid nodes in lattice order, -1 on solid
+    std::vector<int32_t> fidx_h;  // host copy
+    // gathered chunks (variant 8): the compact order of their fields (gidx,
+    // tiles of 8^3 nodes), chunk table, halo lists, neighbour slots, lattice
+    // index and adsorbed-field index per compact node, adsorbed-field index
+    // per interface slot (aperm); host copies of gidx and aperm
+    int32_t *gidx, *gnode, *gaslot, *ghsrc, *aperm;
+    int4* gch;
+    uint16_t* gnbr;
+    int64_t nch = 0;
+    bool gather_ok = false;
+    std::vector<int32_t> gidx_h, aperm_h;
 };
 
 }  // namespace lbmp
@@ -1582,6 +1856,8 @@ constexpr int GRAPH_CHUNK = 64;
 
 int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
+    // variant 8: two reduction tiles (halves) per chunk of GCH fluid nodes
+    if (variant == 8) return 2 * ((f->nf + GCH - 1) / GCH);
     // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
     // (variant 5: the same with full rows)
     if (variant == 3 || variant == 5)
@@ -1610,6 +1886,16 @@ void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
     g.X1 = c.take<T>(S * 4 * N);
     g.Xa = c.take<T>(S * 4 * NIa);
     g.fidx = c.take<int32_t>(N);
+    {
+        const int64_t NF = std::max<int64_t>(g.nf, 1), nch = (NF + GCH - 1) / GCH;
+        g.gidx = c.take<int32_t>(N);
+        g.gnode = c.take<int32_t>(NF);
+        g.gaslot = c.take<int32_t>(NF);
+        g.gch = c.take<int4>(nch);
+        g.ghsrc = c.take<int32_t>(nch * GREG);
+        g.gnbr = c.take<uint16_t>(NL * NF);
+        g.aperm = c.take<int32_t>(NIa);
+    }
     g.coef = c.take<T>(S * 4);
     g.prob = c.take<T>(S * 2);
     g.part = c.take<double>(S * g.ntile_max * NRED);
@@ -1689,7 +1975,7 @@ lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species,
         g.NI = g.flow->ni;
         g.nf = g.flow->nf;
         g.ntile_max = std::max({ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1), ntile_for(g.flow, 1, 3),
-                                ntile_for(g.flow, 2, 3), ntile_for(g.flow, 2, 4)});
+                                ntile_for(g.flow, 2, 3), ntile_for(g.flow, 2, 4), ntile_for(g.flow, 2, 8)});
     }
     return h;
 }
@@ -1704,6 +1990,7 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
             else if (h->variant == 5) k_mp_dma<2, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 6) k_mp_dma<2, true, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 7) k_mp_dma<2, true, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 8) k_mp_gather<<<grid, GCH, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->K == 2) k_mp_dma<2, false, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else k_mp_dma<1, false, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
         }
@@ -1754,7 +2041,13 @@ void do_steps(lbmp_mp* h, int64_t n, hipStream_t s) {
 // and be fetched and written back with them); the other variants, and the
 // full-row blocks, whose 16-byte copies take 4 consecutive nodes, keep the
 // dense layout.
-bool compact_fields(const lbmp_mp* h) { return h->variant == 3 || h->variant == 4 || h->variant == 7; }
+bool compact_fields(const lbmp_mp* h) {
+    return h->variant == 3 || h->variant == 4 || h->variant == 7 || h->variant == 8;
+}
+// node -> compact index map of the chosen variant (null: dense fields)
+const int32_t* cidx(const lbmp_mp* h, const GeomHost& g) {
+    return !compact_fields(h) ? nullptr : (h->variant == 8 ? g.gidx : g.fidx);
+}
 
 // Fill the device geometry table for the current (K, gsz).
 template <typename T>
@@ -1776,7 +2069,8 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
-        d.fidx = compact_fields(h) ? g.fidx : nullptr;
+        d.fidx = cidx(h, g);
+        d.gch = g.gch; d.ghsrc = g.ghsrc; d.gnode = g.gnode; d.gaslot = g.gaslot; d.gnbr = g.gnbr;
         d.NC = compact_fields(h) ? g.nf : g.N;
         d.coef = (const T*)g.coef; d.prob = (const T*)g.prob;
         d.kc = g.kc;
@@ -1883,8 +2177,10 @@ void tune_cache_write(const std::string& key, const TuneVal& v, double ms) {
 bool tile_allowed(const lbmp_mp* h, int v, int K, int gs) {
     const bool ok01 = (v == 0 || v == 1) && (K == 1 || K == 2) && gs >= 1;
     const bool ok2 = v == 2 && K >= 1 && (gs == 1 || gs == 2 || gs == 4) && march_fits(h, gs);
+    bool gather = true;
+    for (const auto& g : h->g) gather = gather && g.gather_ok;
     const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || ((v == 4 || v == 7) && K == 2) ||
-                      ((v == 5 || v == 6) && K == 2 && full_rows(h))) &&
+                      ((v == 5 || v == 6) && K == 2 && full_rows(h)) || (v == 8 && K == 2 && gather)) &&
                      gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
     return ok01 || ok2 || ok3;
 }
@@ -1917,8 +2213,8 @@ lbmp_status autotune(lbmp_mp* h) {
                                  "variant 2 with K = z-segment and 1|2|4 species per block, or variant 3 "
                                  "(FP32 only) with K = 1 or 2 (block height in 64 x 4 tiles), or variant 4 (FP32 only) with K = 2 "
                                  "(z-planes per block), or variants 5, 6 (variants 3, 4 with full rows: FP32, nx = 64 in every "
-                                 "geometry) with K = 2, or variant 7 (variant 4 with lane compaction, FP32) with K = 2; "
-                                 "at most 64 species per block for 3-7");
+                                 "geometry) with K = 2, or variant 7 (variant 4 with lane compaction, FP32) with K = 2, "
+                                 "or variant 8 (gathered chunks, FP32) with K = 2; at most 64 species per block for 3-8");
     }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
@@ -1968,6 +2264,7 @@ lbmp_status autotune(lbmp_mp* h) {
                     cand.push_back({K, gs, 5});
                     cand.push_back({K, gs, 6});
                 }
+                if (K == 2 && (gs <= maxS || gs == 2) && tile_allowed(h, 8, 2, gs)) cand.push_back({K, gs, 8});
             }
     hipEvent_t e0, e1;
     LBMP_HIP(hipEventCreate(&e0));
@@ -2139,7 +2436,7 @@ lbmp_status compact_links(lbmp_mp* h, GeomHost& g, hipStream_t s) {
         using V = decltype(tag);
         V* tmp = reinterpret_cast<V*>(h->setup_tmp);
         dim3 grid((unsigned)((N + BLK - 1) / BLK), (unsigned)rows);
-        k_gather_fluid<V><<<grid, BLK, 0, s>>>(g.fidx, N, static_cast<const V*>(buf), tmp);
+        k_gather_fluid<V><<<grid, BLK, 0, s>>>(cidx(h, g), N, static_cast<const V*>(buf), tmp);
         LBMP_HIP(hipGetLastError());
         LBMP_HIP(hipMemcpyAsync(buf, tmp, (size_t)rows * N * es, hipMemcpyDeviceToDevice, s));
         return LBMP_OK;
@@ -2164,6 +2461,102 @@ lbmp_status build_fidx(GeomHost& g, hipStream_t s) {
                                (long long)g.nf);
     LBMP_HIP(hipMemcpyAsync(g.fidx, fi.data(), g.N * 4, hipMemcpyHostToDevice, s));
     LBMP_HIP(hipStreamSynchronize(s));
+    g.fidx_h = std::move(fi);
+    return LBMP_OK;
+}
+
+// Tables of the gathered-chunk blocks (variant 8) for geometry g. The compact
+// order runs over tiles of GTILE^3 lattice nodes (x fastest, then y, z) and,
+// within a tile, over its fluid nodes in lattice order; chunk c takes compact
+// nodes c GCH .. c GCH + GCH - 1. Its halo lists, sorted, the fluid nodes
+// outside the chunk its nodes pull from (r - c_k), and each node's 18 arrivals
+// get their region slot: the chunk node's own position, GCH.. for the halo in
+// list order, GZSLOT for a solid r - c_k. A chunk whose nodes and halo exceed
+// the region leaves gather_ok false (the tuner then does not offer the
+// variant for the workload).
+lbmp_status build_gather(GeomHost& g, hipStream_t s) {
+    g.gather_ok = false;
+    const lbmp_flow* f = g.flow;
+    const int nx = f->nx, ny = f->ny, nz = f->nz;
+    const int64_t N = g.N;
+    std::vector<int8_t> cls(N);
+    std::vector<int32_t> slot(N);
+    LBMP_HIP(hipMemcpyAsync(cls.data(), f->d.cls, N, hipMemcpyDeviceToHost, s));
+    LBMP_HIP(hipMemcpyAsync(slot.data(), f->d.slot, N * 4, hipMemcpyDeviceToHost, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> gidx(N, -1), gnode;
+    gnode.reserve(g.nf);
+    for (int tz = 0; tz < nz; tz += GTILE)
+        for (int ty = 0; ty < ny; ty += GTILE)
+            for (int tx = 0; tx < nx; tx += GTILE)
+                for (int z = tz; z < std::min(nz, tz + GTILE); ++z)
+                    for (int y = ty; y < std::min(ny, ty + GTILE); ++y)
+                        for (int x = tx; x < std::min(nx, tx + GTILE); ++x) {
+                            const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                            if (cls[n]) {
+                                gidx[n] = (int32_t)gnode.size();
+                                gnode.push_back((int32_t)n);
+                            }
+                        }
+    const int64_t NF = (int64_t)gnode.size();
+    if (NF != g.nf) return fail(LBMP_ESTATE, "fluid node count %lld differs from the flow's %lld", (long long)NF,
+                                (long long)g.nf);
+    std::vector<int32_t> gaslot(NF, -1), aperm(std::max<int64_t>(g.NI, 1), 0);
+    int32_t ai = 0;
+    for (int64_t i = 0; i < NF; ++i)
+        if (cls[gnode[i]] == 2) {
+            gaslot[i] = ai;
+            aperm[slot[gnode[i]]] = ai++;
+        }
+    const int64_t nch = (NF + GCH - 1) / GCH;
+    std::vector<int4> chs(nch);
+    std::vector<int32_t> hsrc, halo, pos(NF, -1);
+    std::vector<uint16_t> nbr((size_t)NL * NF);
+    auto from = [&](int64_t n, int k) {  // lattice index of r - c_k (periodic)
+        const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        return (int64_t)wrapi(x - lcx(k), nx) + (int64_t)nx * (wrapi(y - lcy(k), ny) + (int64_t)ny * wrapi(z - lcz(k), nz));
+    };
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t base = c * GCH, C = std::min<int64_t>(GCH, NF - base);
+        halo.clear();
+        for (int64_t i = base; i < base + C; ++i)
+            for (int k = 0; k < NL; ++k) {
+                const int64_t m = from(gnode[i], k);
+                if (!cls[m]) continue;
+                const int32_t j = gidx[m];
+                if (j < base || j >= base + C) halo.push_back(j);
+            }
+        std::sort(halo.begin(), halo.end());
+        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+        const int64_t H = (int64_t)halo.size();
+        if (C + H > GZSLOT) return LBMP_OK;  // region too small: variant not offered
+        for (int64_t e = 0; e < H; ++e) pos[halo[e]] = (int32_t)(C + e);
+        for (int64_t i = base; i < base + C; ++i)
+            for (int k = 0; k < NL; ++k) {
+                const int64_t m = from(gnode[i], k);
+                int32_t sl = GZSLOT;
+                if (cls[m]) {
+                    const int32_t j = gidx[m];
+                    sl = (j >= base && j < base + C) ? (int32_t)(j - base) : pos[j];
+                }
+                nbr[(size_t)k * NF + i] = (uint16_t)sl;
+            }
+        for (int64_t e = 0; e < H; ++e) pos[halo[e]] = -1;
+        chs[c] = make_int4((int)base, (int)C, (int)hsrc.size(), (int)H);
+        hsrc.insert(hsrc.end(), halo.begin(), halo.end());
+    }
+    LBMP_HIP(hipMemcpyAsync(g.gidx, gidx.data(), N * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.gnode, gnode.data(), NF * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.gaslot, gaslot.data(), NF * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.gch, chs.data(), nch * sizeof(int4), hipMemcpyHostToDevice, s));
+    if (!hsrc.empty()) LBMP_HIP(hipMemcpyAsync(g.ghsrc, hsrc.data(), hsrc.size() * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.gnbr, nbr.data(), nbr.size() * 2, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipMemcpyAsync(g.aperm, aperm.data(), aperm.size() * 4, hipMemcpyHostToDevice, s));
+    LBMP_HIP(hipStreamSynchronize(s));
+    g.nch = nch;
+    g.gidx_h = std::move(gidx);
+    g.aperm_h = std::move(aperm);
+    g.gather_ok = true;
     return LBMP_OK;
 }
 
@@ -2180,8 +2573,7 @@ lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
         LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * N * sizeof(T), s));
         LBMP_HIP(hipMemsetAsync(g.Xa, 0, (size_t)g.S * 4 * std::max<int64_t>(g.NI, 1) * sizeof(T), s));
         dim3 grid((unsigned)((N + BLK - 1) / BLK), (unsigned)g.S);
-        k_init_uptake<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, N, 1.0 / (double)g.nf,
-                                              compact_fields(h) ? g.fidx : nullptr,
+        k_init_uptake<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, N, 1.0 / (double)g.nf, cidx(h, g),
                                               compact_fields(h) ? g.nf : N, (T*)g.X1);
         LBMP_HIP(hipGetLastError());
         return LBMP_OK;
@@ -2189,8 +2581,8 @@ lbmp_status init_state(lbmp_mp* h, GeomHost& g, hipStream_t s) {
     dim3 grid((unsigned)((std::max<int64_t>(N, g.NI) + BLK - 1) / BLK), (unsigned)g.S);
     const double* w = g.bmu.empty() ? nullptr : setup_bmu(h->setup_tmp, N) + N;
     k_init_state<T><<<grid, BLK, 0, s>>>(g.flow->d.cls, g.flow->d.ilist, N, g.NI, g.S, g.spc, b64, src64, w,
-                                         compact_fields(h) ? g.fidx : nullptr, compact_fields(h) ? g.nf : N,
-                                         (T*)g.X1, (T*)g.Xa);
+                                         cidx(h, g), compact_fields(h) ? g.nf : N,
+                                         h->variant == 8 ? g.aperm : nullptr, (T*)g.X1, (T*)g.Xa);
     LBMP_HIP(hipGetLastError());
     return LBMP_OK;
 }
@@ -2205,6 +2597,10 @@ lbmp_status setup_all(lbmp_mp* h, hipStream_t s) {
         if (st != LBMP_OK) return st;
         st = build_fidx(g, s);
         if (st != LBMP_OK) return st;
+        if (h->prec == LBMP_FP32) {
+            st = build_gather(g, s);
+            if (st != LBMP_OK) return st;
+        }
         LBMP_HIP(hipMemsetAsync(g.X0, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
         LBMP_HIP(hipMemsetAsync(g.X1, 0, (size_t)g.S * 4 * g.N * sizeof(T), s));
         LBMP_HIP(hipMemsetAsync(g.Xa, 0, (size_t)g.S * 4 * std::max<int64_t>(g.NI, 1) * sizeof(T), s));
@@ -2537,18 +2933,20 @@ extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, do
                        : reinterpret_cast<const double*>(v.data())[i];
     };
     const double rr = g.rho_ref[species], gr = g.gam_ref[species];
+    // where node n's fields and interface slot i's adsorbed fields are stored
+    const std::vector<int32_t>* map = !compact_fields(h) ? nullptr : (h->variant == 8 ? &g.gidx_h : &g.fidx_h);
+    const bool perm = h->variant == 8;
     for (int q = 0; q < 4; ++q) {
         const double cq = q == 0 ? 1.0 : g.V[3 * species + q - 1];
-        int64_t i = 0;  // index among the fluid nodes
         for (int64_t n = 0; n < N; ++n) {
             const double wn = g.w.empty() ? 1.0 : g.w[n];
-            if (X) X[q * N + n] = cls[n] ? at(hx, q * NC + (NC == N ? n : i)) + cq * rr * wn : 0.0;
-            if (cls[n]) ++i;
+            if (X) X[q * N + n] = cls[n] ? at(hx, q * NC + (map ? (*map)[n] : n)) + cq * rr * wn : 0.0;
         }
         if (Xads) {
             for (int64_t n = 0; n < N; ++n) Xads[q * N + n] = 0.0;
             for (int64_t i = 0; i < NI; ++i)
-                Xads[q * N + ilist[i]] = at(ha, q * NIa + i) + cq * gr * (g.w.empty() ? 1.0 : g.w[ilist[i]]);
+                Xads[q * N + ilist[i]] =
+                    at(ha, q * NIa + (perm ? g.aperm_h[i] : i)) + cq * gr * (g.w.empty() ? 1.0 : g.w[ilist[i]]);
         }
     }
     return LBMP_OK;

@@ -112,7 +112,7 @@ def test_periodic_potential_effective_diffusion(lb):
     fl.free()
 
 
-@pytest.mark.parametrize("tile", ["3,1,2", "6,2,2", "7,2,2"])
+@pytest.mark.parametrize("tile", ["3,1,2", "6,2,2", "7,2,2", "8,2,2"])
 def test_lds_dma_kernels_with_potential(lb, tile):
     """The tuned FP32 step kernels (haloed, full-row, lane-compacted blocks)
     propagate the charged set-up like the oracle."""
