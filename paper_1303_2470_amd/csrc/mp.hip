@@ -1238,7 +1238,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
 
 // ------------------------------------------------------------------ gathered chunks
 // Variant 8: a block updates one chunk of up to GCH fluid nodes that are
-// consecutive in the compact storage, whose order (tiles of 8 x 8 x 8 lattice
+// consecutive in the compact storage, whose order (tiles of 32 x 4 x 4 lattice
 // nodes, fluid nodes in lattice order within a tile) keeps a chunk spatially
 // compact. Per field the buffer unit copies the chunk's own values (one
 // contiguous range) and those of its halo (the fluid nodes outside the chunk
@@ -1252,7 +1252,7 @@ constexpr int GCH = 2 * BLK;                     // nodes per chunk, threads per
 constexpr int GRLD = 3;                          // region copies per thread and field
 constexpr int GREG = GRLD * GCH;                 // region slots: chunk, halo, zeros
 constexpr int GZSLOT = GREG - 1;                 // never filled: reads 0
-constexpr int GTILE = 8;                         // edge of the ordering tiles
+constexpr int GTX = 32, GTY = 4, GTZ = 4;        // ordering tiles (compact storage)
 
 __global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k_mp_gather(
     const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
@@ -1854,10 +1854,14 @@ namespace {
 
 constexpr int GRAPH_CHUNK = 64;
 
+int64_t gather_chunk_cap(int64_t nf) { return 2 * ((std::max<int64_t>(nf, 1) + GCH - 1) / GCH); }
+
 int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
-    // variant 8: two reduction tiles (halves) per chunk of GCH fluid nodes
-    if (variant == 8) return 2 * ((f->nf + GCH - 1) / GCH);
+    // variant 8: two reduction tiles (halves) per chunk of at most GCH fluid
+    // nodes; chunks are cut shorter where their halo would not fit, up to
+    // twice the count of full chunks (the capacity reserved)
+    if (variant == 8) return 2 * gather_chunk_cap(f->nf);
     // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
     // (variant 5: the same with full rows)
     if (variant == 3 || variant == 5)
@@ -1887,7 +1891,7 @@ void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
     g.Xa = c.take<T>(S * 4 * NIa);
     g.fidx = c.take<int32_t>(N);
     {
-        const int64_t NF = std::max<int64_t>(g.nf, 1), nch = (NF + GCH - 1) / GCH;
+        const int64_t NF = std::max<int64_t>(g.nf, 1), nch = gather_chunk_cap(NF);
         g.gidx = c.take<int32_t>(N);
         g.gnode = c.take<int32_t>(NF);
         g.gaslot = c.take<int32_t>(NF);
@@ -2063,7 +2067,7 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.pb = (int)(((int64_t)f->nx * f->ny + BLK - 1) / BLK);
         d.zb = (f->nz + h->K - 1) / h->K;
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
-        d.ntile = ntile_for(f, h->K, h->variant);
+        d.ntile = h->variant == 8 ? 2 * g.nch : ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
         blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3-7: one block per K tiles
         d.cls = f->d.cls; d.slot = f->d.slot;
@@ -2466,8 +2470,8 @@ lbmp_status build_fidx(GeomHost& g, hipStream_t s) {
 }
 
 // Tables of the gathered-chunk blocks (variant 8) for geometry g. The compact
-// order runs over tiles of GTILE^3 lattice nodes (x fastest, then y, z) and,
-// within a tile, over its fluid nodes in lattice order; chunk c takes compact
+// order runs over tiles of GTX x GTY x GTZ lattice nodes and, within a
+// tile, over its fluid nodes in lattice order; chunk c takes compact
 // nodes c GCH .. c GCH + GCH - 1. Its halo lists, sorted, the fluid nodes
 // outside the chunk its nodes pull from (r - c_k), and each node's 18 arrivals
 // get their region slot: the chunk node's own position, GCH.. for the halo in
@@ -2484,14 +2488,27 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
     LBMP_HIP(hipMemcpyAsync(cls.data(), f->d.cls, N, hipMemcpyDeviceToHost, s));
     LBMP_HIP(hipMemcpyAsync(slot.data(), f->d.slot, N * 4, hipMemcpyDeviceToHost, s));
     LBMP_HIP(hipStreamSynchronize(s));
+    // tiles of GTX x GTY x GTZ nodes, x fastest then y, z; long in x, so that
+    // the halo a chunk pulls across its y and z faces comes in runs of up to
+    // GTX consecutive compact nodes (whole cache lines) and its x faces are small
+    // LBMP_GATHER_TILE="tx,ty,tz" overrides the tile shape (experiments)
+    int gtx = GTX, gty = GTY, gtz = GTZ;
+    if (const char* e = getenv("LBMP_GATHER_TILE")) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
+            gtx = a;
+            gty = b;
+            gtz = c;
+        }
+    }
     std::vector<int32_t> gidx(N, -1), gnode;
     gnode.reserve(g.nf);
-    for (int tz = 0; tz < nz; tz += GTILE)
-        for (int ty = 0; ty < ny; ty += GTILE)
-            for (int tx = 0; tx < nx; tx += GTILE)
-                for (int z = tz; z < std::min(nz, tz + GTILE); ++z)
-                    for (int y = ty; y < std::min(ny, ty + GTILE); ++y)
-                        for (int x = tx; x < std::min(nx, tx + GTILE); ++x) {
+    for (int tz = 0; tz < nz; tz += gtz)
+        for (int ty = 0; ty < ny; ty += gty)
+            for (int tx = 0; tx < nx; tx += gtx)
+                for (int z = tz; z < std::min(nz, tz + gtz); ++z)
+                    for (int y = ty; y < std::min(ny, ty + gty); ++y)
+                        for (int x = tx; x < std::min(nx, tx + gtx); ++x) {
                             const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
                             if (cls[n]) {
                                 gidx[n] = (int32_t)gnode.size();
@@ -2508,16 +2525,15 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
             gaslot[i] = ai;
             aperm[slot[gnode[i]]] = ai++;
         }
-    const int64_t nch = (NF + GCH - 1) / GCH;
-    std::vector<int4> chs(nch);
+    const int64_t cap = gather_chunk_cap(NF);
+    std::vector<int4> chs;
     std::vector<int32_t> hsrc, halo, pos(NF, -1);
     std::vector<uint16_t> nbr((size_t)NL * NF);
     auto from = [&](int64_t n, int k) {  // lattice index of r - c_k (periodic)
         const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
         return (int64_t)wrapi(x - lcx(k), nx) + (int64_t)nx * (wrapi(y - lcy(k), ny) + (int64_t)ny * wrapi(z - lcz(k), nz));
     };
-    for (int64_t c = 0; c < nch; ++c) {
-        const int64_t base = c * GCH, C = std::min<int64_t>(GCH, NF - base);
+    auto halo_of = [&](int64_t base, int64_t C) {
         halo.clear();
         for (int64_t i = base; i < base + C; ++i)
             for (int k = 0; k < NL; ++k) {
@@ -2528,8 +2544,18 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
             }
         std::sort(halo.begin(), halo.end());
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+    };
+    for (int64_t base = 0; base < NF;) {
+        // the longest chunk (up to GCH nodes, in steps of 64) whose halo fits
+        int64_t C = std::min<int64_t>(GCH, NF - base);
+        halo_of(base, C);
+        while (C + (int64_t)halo.size() > GZSLOT && C > 64) {
+            C = std::max<int64_t>(64, C - 64);
+            halo_of(base, C);
+        }
         const int64_t H = (int64_t)halo.size();
-        if (C + H > GZSLOT) return LBMP_OK;  // region too small: variant not offered
+        if (C + H > GZSLOT || (int64_t)chs.size() >= cap || (int64_t)hsrc.size() + H > cap * GREG)
+            return LBMP_OK;  // does not fit the reserved tables: variant not offered
         for (int64_t e = 0; e < H; ++e) pos[halo[e]] = (int32_t)(C + e);
         for (int64_t i = base; i < base + C; ++i)
             for (int k = 0; k < NL; ++k) {
@@ -2542,9 +2568,11 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
                 nbr[(size_t)k * NF + i] = (uint16_t)sl;
             }
         for (int64_t e = 0; e < H; ++e) pos[halo[e]] = -1;
-        chs[c] = make_int4((int)base, (int)C, (int)hsrc.size(), (int)H);
+        chs.push_back(make_int4((int)base, (int)C, (int)hsrc.size(), (int)H));
         hsrc.insert(hsrc.end(), halo.begin(), halo.end());
+        base += C;
     }
+    const int64_t nch = (int64_t)chs.size();
     LBMP_HIP(hipMemcpyAsync(g.gidx, gidx.data(), N * 4, hipMemcpyHostToDevice, s));
     LBMP_HIP(hipMemcpyAsync(g.gnode, gnode.data(), NF * 4, hipMemcpyHostToDevice, s));
     LBMP_HIP(hipMemcpyAsync(g.gaslot, gaslot.data(), NF * 4, hipMemcpyHostToDevice, s));
