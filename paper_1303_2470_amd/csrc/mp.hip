@@ -1248,15 +1248,25 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
 // thread has a fluid node, whatever the porosity, and only fluid values are
 // copied. The arithmetic, its order and the rounding bits are those of the
 // LDS-DMA blocks, so the stored fields are bitwise the same.
-constexpr int GCH = 2 * BLK;                     // nodes per chunk, threads per block
-constexpr int GRLD = 3;                          // region copies per thread and field
-constexpr int GREG = GRLD * GCH;                 // region slots: chunk, halo, zeros
-constexpr int GZSLOT = GREG - 1;                 // never filled: reads 0
+// NH = 1 or 2: blocks of 256 or 512 threads (nodes per chunk); the region
+// holds 4 or 3 slots per thread
+template <int NH>
+struct GatherShape {
+    static constexpr int DBLK = NH * BLK;                 // nodes per chunk, threads per block
+    static constexpr int RLD = NH == 1 ? 4 : 3;           // region copies per thread and field
+    static constexpr int REG = RLD * DBLK;                // region slots: chunk, halo, zeros
+    static constexpr int ZSLOT = REG - 1;                 // never filled: reads 0
+};
+constexpr int GCH = 2 * BLK;                     // the largest chunk
+constexpr int GREG = GatherShape<2>::REG;        // the largest region
 constexpr int GTX = 32, GTY = 4, GTZ = 4;        // ordering tiles (compact storage)
 
-__global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k_mp_gather(
+template <int NH>
+__global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_gather(
     const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
-    constexpr int DBLK = GCH, RLD = GRLD, NCP = GRLD, REGION = GREG, STAGE = GREG + GCH;
+    using GS = GatherShape<NH>;
+    constexpr int DBLK = GS::DBLK, RLD = GS::RLD, NCP = GS::RLD, REGION = GS::REG, STAGE = GS::REG + DBLK;
+    constexpr int GZSLOT = GS::ZSLOT;
     constexpr int NW = DBLK / 64;
     constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2, WAIT_IDLE = 2 * NCP;
     __shared__ __align__(16) float st0[STAGE];
@@ -1264,7 +1274,7 @@ __global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k
     __shared__ __align__(16) float st2[STAGE];
     __shared__ __align__(16) float st3[STAGE];
     __shared__ __align__(16) double rl[NSUM * DBLK];
-    __shared__ __align__(16) double l2[2 * NRED * 64];
+    __shared__ __align__(16) double l2[NH * NRED * 64];
     float* const tag = nullptr;
     const int64_t lb = xcd_remap(blockIdx.x, nblocks);
     const int gi = find_geom(geoms, ngeom, lb);
@@ -1277,7 +1287,7 @@ __global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
     const int hf = wv >> 2, w4 = wv & 3;
-    const int64_t tile = 2 * chunk + hf;          // reduction tiles: the two halves of the chunk
+    const int64_t tile = NH * chunk + hf;         // reduction tiles: the halves (NH = 2) of the chunk
     const int NI = (int)G.NI, S = G.S;
     const int NC = (int)G.NC;
     const int s0 = grp * gsz, s1 = min(S, s0 + gsz);
@@ -1340,10 +1350,11 @@ __global__ void __launch_bounds__(GCH) __attribute__((amdgpu_waves_per_eu(4))) k
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + (j / GJ) * GJ * DBLK), 4, vo[j], qp * NB,
                                                      (j % GJ) * DBLK * 4, 0);
         };
-        static_assert(NCP == 3, "three region copies per field");
+        static_assert(NCP == 3 || NCP == 4, "three or four region copies per field");
         copy(std::integral_constant<int, 0>());
         copy(std::integral_constant<int, 1>());
         copy(std::integral_constant<int, 2>());
+        if constexpr (NCP == 4) copy(std::integral_constant<int, 3>());
         if constexpr (decltype(anyc)::value) {
             const auto rina = mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa,
@@ -1823,6 +1834,7 @@ struct GeomHost {
     int4* gch;
     uint16_t* gnbr;
     int64_t nch = 0;
+    int gnh = 2;  // threads per block / 256 of the chunk tables (LBMP_GATHER_NH, default 2)
     bool gather_ok = false;
     std::vector<int32_t> gidx_h, aperm_h;
 };
@@ -1854,13 +1866,14 @@ namespace {
 
 constexpr int GRAPH_CHUNK = 64;
 
-int64_t gather_chunk_cap(int64_t nf) { return 2 * ((std::max<int64_t>(nf, 1) + GCH - 1) / GCH); }
+// chunks reserved per geometry: twice the count of full chunks of the
+// smaller block (256 nodes)
+int64_t gather_chunk_cap(int64_t nf) { return 2 * ((std::max<int64_t>(nf, 1) + BLK - 1) / BLK); }
 
 int64_t ntile_for(const lbmp_flow* f, int K, int variant) {
     const int64_t zb = (f->nz + K - 1) / K;  // K = z-planes per tile (z-segment for variant 2)
-    // variant 8: two reduction tiles (halves) per chunk of at most GCH fluid
-    // nodes; chunks are cut shorter where their halo would not fit, up to
-    // twice the count of full chunks (the capacity reserved)
+    // variant 8: up to two reduction tiles (halves) per chunk; chunks are cut
+    // shorter where their halo would not fit, up to the capacity reserved
     if (variant == 8) return 2 * gather_chunk_cap(f->nf);
     // variant 3: K reduction tiles (TX x TY) per block of TX x (K TY), one z-plane
     // (variant 5: the same with full rows)
@@ -1896,7 +1909,7 @@ void carve_geom(GeomHost& g, Carver& c, int64_t tmax) {
         g.gnode = c.take<int32_t>(NF);
         g.gaslot = c.take<int32_t>(NF);
         g.gch = c.take<int4>(nch);
-        g.ghsrc = c.take<int32_t>(nch * GREG);
+        g.ghsrc = c.take<int32_t>(nch * GatherShape<1>::REG);
         g.gnbr = c.take<uint16_t>(NL * NF);
         g.aperm = c.take<int32_t>(NIa);
     }
@@ -1994,7 +2007,8 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
             else if (h->variant == 5) k_mp_dma<2, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 6) k_mp_dma<2, true, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 7) k_mp_dma<2, true, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
-            else if (h->variant == 8) k_mp_gather<<<grid, GCH, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 8 && h->g[0].gnh == 1) k_mp_gather<1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 8) k_mp_gather<2><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->K == 2) k_mp_dma<2, false, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else k_mp_dma<1, false, false><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
         }
@@ -2067,9 +2081,10 @@ lbmp_status upload_geoms(lbmp_mp* h) {
         d.pb = (int)(((int64_t)f->nx * f->ny + BLK - 1) / BLK);
         d.zb = (f->nz + h->K - 1) / h->K;
         d.ngrp = (g.S + h->gsz - 1) / h->gsz;
-        d.ntile = h->variant == 8 ? 2 * g.nch : ntile_for(f, h->K, h->variant);
+        d.ntile = h->variant == 8 ? g.gnh * g.nch : ntile_for(f, h->K, h->variant);
         d.blk0 = blk;
-        blk += (h->variant >= 3 ? d.ntile / h->K : d.ntile) * d.ngrp;  // variants 3-7: one block per K tiles
+        // variants 3-7: one block per K tiles; variant 8: one per chunk
+        blk += (h->variant == 8 ? g.nch : (h->variant >= 3 ? d.ntile / h->K : d.ntile)) * d.ngrp;
         d.cls = f->d.cls; d.slot = f->d.slot;
         d.pin = (const T*)g.pin; d.sig = (const double*)g.sig; d.src = (const T*)g.src; d.a = (const T*)g.a;
         d.X0 = (T*)g.X0; d.X1 = (T*)g.X1; d.Xa = (T*)g.Xa;
@@ -2525,6 +2540,10 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
             gaslot[i] = ai;
             aperm[slot[gnode[i]]] = ai++;
         }
+    g.gnh = 2;
+    if (const char* e = getenv("LBMP_GATHER_NH")) g.gnh = atoi(e) == 1 ? 1 : 2;
+    const int64_t CH = (int64_t)g.gnh * BLK;                      // nodes per chunk
+    const int64_t ZS = g.gnh == 1 ? GatherShape<1>::ZSLOT : GatherShape<2>::ZSLOT;
     const int64_t cap = gather_chunk_cap(NF);
     std::vector<int4> chs;
     std::vector<int32_t> hsrc, halo, pos(NF, -1);
@@ -2546,21 +2565,21 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
     };
     for (int64_t base = 0; base < NF;) {
-        // the longest chunk (up to GCH nodes, in steps of 64) whose halo fits
-        int64_t C = std::min<int64_t>(GCH, NF - base);
+        // the longest chunk (up to CH nodes, in steps of 64) whose halo fits
+        int64_t C = std::min<int64_t>(CH, NF - base);
         halo_of(base, C);
-        while (C + (int64_t)halo.size() > GZSLOT && C > 64) {
+        while (C + (int64_t)halo.size() > ZS && C > 64) {
             C = std::max<int64_t>(64, C - 64);
             halo_of(base, C);
         }
         const int64_t H = (int64_t)halo.size();
-        if (C + H > GZSLOT || (int64_t)chs.size() >= cap || (int64_t)hsrc.size() + H > cap * GREG)
+        if (C + H > ZS || (int64_t)chs.size() >= cap || (int64_t)hsrc.size() + H > cap * GatherShape<1>::REG)
             return LBMP_OK;  // does not fit the reserved tables: variant not offered
         for (int64_t e = 0; e < H; ++e) pos[halo[e]] = (int32_t)(C + e);
         for (int64_t i = base; i < base + C; ++i)
             for (int k = 0; k < NL; ++k) {
                 const int64_t m = from(gnode[i], k);
-                int32_t sl = GZSLOT;
+                int32_t sl = (int32_t)ZS;
                 if (cls[m]) {
                     const int32_t j = gidx[m];
                     sl = (j >= base && j < base + C) ? (int32_t)(j - base) : pos[j];

@@ -46,10 +46,12 @@ def run(lb, monkeypatch, tile, flow, params, T, species=(), uptake=False):
 @pytest.mark.parametrize("shape,frac,seed", [((70, 9, 7), 0.3, 61), ((21, 13, 11), 0.5, 62), ((130, 5, 9), 0.8, 63),
                                              ((16, 16, 16), 0.0, 64)])
 @pytest.mark.parametrize("gs", [1, 3, 5])
-def test_gather_vs_block_and_oracle(lb, monkeypatch, shape, frac, seed, gs):
-    """Random porous lattices (ragged against the 8^3 ordering tiles, solid
+@pytest.mark.parametrize("nh", [1, 2])
+def test_gather_vs_block_and_oracle(lb, monkeypatch, shape, frac, seed, gs, nh):
+    """Random porous lattices (ragged against the ordering tiles, solid
     fractions 0 to 0.8), random velocity, five species (one without
-    adsorption)."""
+    adsorption); blocks of 256 and 512 threads."""
+    monkeypatch.setenv("LBMP_GATHER_NH", str(nh))
     m = inputs.random_mask(*shape, frac, seed=seed)
     u = inputs.random_velocity(m, 0.02, seed=seed + 100)
     ka = np.array([0.0, 0.02, 0.1, 0.005, 0.3])
