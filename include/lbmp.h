@@ -235,7 +235,8 @@ typedef struct {
     double min_stay;       /* smallest stay probability over species */
     double mean_velocity[3];
     int tile_k;            /* variants 0, 1: z-planes per thread; 2: z-segment per block;
-                              3, 5: block height in 64 x 4 tiles; 4, 6, 7: planes per block */
+                              3, 5: block height in 64 x 4 tiles; 4, 6, 7: planes per block
+                              (2; 4 for variant 6 when pinned); 8: 2 */
     int species_per_block; /* species per block chosen by the tile tuner */
     int kernel_variant;    /* 0: direct neighbour loads, 1: fields staged through LDS,
                               2: z-march with an LDS plane ring, 3: LDS-DMA copies (FP32),
@@ -243,7 +244,10 @@ typedef struct {
                               variants 3 (64 x 8) and 4 with whole periodic rows, for
                               lattices 64 nodes wide (FP32; every geometry nx = 64), 7:
                               variant 4 with its fluid nodes packed onto the first
-                              threads of a block (FP32; porous media). The
+                              threads of a block (FP32; porous media), 8: gathered
+                              chunks of up to 512 fluid nodes consecutive in a
+                              tile-ordered compact storage, their halo copied
+                              by per-node lists (FP32; porous media). The
                               tuner times them in mp_init; the environment variable
                               LBMP_TILE = "variant,tile_k,species_per_block" pins one
                               (mp_init returns LBMP_EINVAL for a choice the lattice or

@@ -1992,7 +1992,8 @@ lbmp_mp* make_handle(const lbmp_flow* const* flows, const lbmp_species* species,
         g.NI = g.flow->ni;
         g.nf = g.flow->nf;
         g.ntile_max = std::max({ntile_for(g.flow, 1, 0), ntile_for(g.flow, 1, 1), ntile_for(g.flow, 1, 3),
-                                ntile_for(g.flow, 2, 3), ntile_for(g.flow, 2, 4), ntile_for(g.flow, 2, 8)});
+                                ntile_for(g.flow, 2, 3), ntile_for(g.flow, 2, 4), ntile_for(g.flow, 4, 6),
+                                ntile_for(g.flow, 2, 8)});
     }
     return h;
 }
@@ -2005,6 +2006,7 @@ void launch_step_kernel(lbmp_mp* h, hipStream_t s) {
         if constexpr (std::is_same<T, float>::value) {
             if (h->variant == 4) k_mp_dma<2, true, false><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 5) k_mp_dma<2, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
+            else if (h->variant == 6 && h->K == 4) k_mp_dma<4, true, true><<<grid, 4 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 6) k_mp_dma<2, true, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 7) k_mp_dma<2, true, false, true><<<grid, 2 * BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
             else if (h->variant == 8 && h->g[0].gnh == 1) k_mp_gather<1><<<grid, BLK, 0, s>>>(G, h->ngeom, h->gsz, h->nblocks, h->ctl);
@@ -2199,7 +2201,8 @@ bool tile_allowed(const lbmp_mp* h, int v, int K, int gs) {
     bool gather = true;
     for (const auto& g : h->g) gather = gather && g.gather_ok;
     const bool ok3 = ((v == 3 && (K == 1 || K == 2)) || ((v == 4 || v == 7) && K == 2) ||
-                      ((v == 5 || v == 6) && K == 2 && full_rows(h)) || (v == 8 && K == 2 && gather)) &&
+                      ((v == 5 || v == 6) && K == 2 && full_rows(h)) || (v == 6 && K == 4 && full_rows(h)) ||
+                      (v == 8 && K == 2 && gather)) &&
                      gs >= 1 && gs <= DMA_GMAX && h->prec == LBMP_FP32 && dma_fits(h);
     return ok01 || ok2 || ok3;
 }

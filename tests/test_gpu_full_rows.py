@@ -129,3 +129,29 @@ def test_full_rows_refused(lb, monkeypatch):
     monkeypatch.setenv("LBMP_TILE", "6,2,1")   # one geometry 70 wide refuses the batch
     with pytest.raises(lb.LbmpError):
         lb.mp_init([f64, f70], [p, p], 32, 10)
+
+
+@pytest.mark.parametrize("shape,seed", [((64, 9, 7), 41), ((64, 3, 5), 42), ((64, 17, 2), 43), ((64, 6, 13), 44)])
+@pytest.mark.parametrize("gs", [1, 3, 64])
+def test_full_rows_four_planes(lb, monkeypatch, shape, seed, gs):
+    """Full-row blocks of four planes (1,024 threads, variant 6 with K = 4):
+    fields bitwise equal to the two-plane block's (same nodes, arithmetic and
+    rounding bits), series to rounding (more, partly empty, reduction tiles),
+    D(t) against the oracle; nz ragged against the four planes."""
+    m = inputs.random_mask(*shape, 0.3, seed=seed)
+    u = inputs.random_velocity(m, 0.02, seed=seed + 100)
+    ka = np.array([0.0, 0.02, 0.1, 0.005, 0.3])
+    kd = np.array([0.1, 0.01, 0.2, 0.5, 0.9])
+    params = {"D_b": 0.06, "k_a": ka, "k_d": kd}
+    T = 150
+    flow = lb.lb_flow_from_velocity(m, u)
+    st, out, fields = run(lb, monkeypatch, f"6,4,{gs}", flow, params, T, species=(1, 4))
+    assert (st["kernel_variant"], st["tile_k"]) == (6, 4)
+    _, ref_out, ref_fields = run(lb, monkeypatch, f"6,2,{gs}", flow, params, T, species=(1, 4))
+    for (X, Xa), (Xr, Xar) in zip(fields, ref_fields):
+        assert np.array_equal(X, Xr) and np.array_equal(Xa, Xar)
+    np.testing.assert_allclose(out["Z"], ref_out["Z"], rtol=1e-12, atol=1e-18)
+    for s in range(5):
+        ref = oracle.vacf(m, u, 0.72, ka[s], kd[s], T)
+        Dref = oracle.d_of_t(ref["Z"], ref["V"])
+        assert d_err(out["D"][s], Dref, 0.06) < 1e-5, s
