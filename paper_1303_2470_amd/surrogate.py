@@ -339,7 +339,8 @@ def main(argv=None):
             x, y, info = run_groups(lbmp, [group_params(s) for s in b], log)
             Xtr.append(x)
             Ytr.append(y)
-        Xtr, Ytr = np.concatenate(Xtr), np.concatenate(Ytr)
+        Xtr = np.concatenate(Xtr) if Xtr else np.zeros((0, 6))
+        Ytr = np.concatenate(Ytr) if Ytr else np.zeros(0)
         t_gen = time.time() - t0
         # held-out media: new seeds; the plain method is timed on them
         Xte, Yte, plain_s, answered = [], [], 0.0, 0
