@@ -233,23 +233,25 @@ def surrogate_throughput(lb, n: int, batch_max: int, train_batch: int, reps: int
     sg.sync()
     tp = (time.perf_counter() - t0) / reps
     sg.free()
-    st = lb.Surrogate(train_batch, seed=1)
-    y = torch.rand((train_batch,), device="cuda", generator=g, dtype=torch.float32)
-    xt = x[:train_batch].contiguous()
-    st.train_step(xt, y, None, train_batch, 1e-4)
-    st.sync()
-    t0 = time.perf_counter()
-    for _ in range(reps * 10):
-        st.train_step(xt, y, None, train_batch, 1e-4)
-    st.sync()
-    tt = (time.perf_counter() - t0) / (reps * 10)
-    st.free()
     peak = 2.5e15
-    return {"metric": "surrogate throughput", "predict_rows": n, "predict_chunk": batch_max,
-            "predict_s": tp, "predict_samples_per_s": n / tp, "predict_tflops": fwd * n / tp / 1e12,
-            "predict_frac_bf16_peak": fwd * n / tp / peak,
-            "train_batch": train_batch, "train_step_s": tt, "train_samples_per_s": train_batch / tt,
-            "train_tflops": 3 * fwd * train_batch / tt / 1e12, "peak_tflops_bf16": peak / 1e12}
+    res = {"metric": "surrogate throughput", "predict_rows": n, "predict_chunk": batch_max,
+           "predict_s": tp, "predict_samples_per_s": n / tp, "predict_tflops": fwd * n / tp / 1e12,
+           "predict_frac_bf16_peak": fwd * n / tp / peak, "peak_tflops_bf16": peak / 1e12, "train": []}
+    for tb in (train_batch, 8 * train_batch):
+        st = lb.Surrogate(tb, seed=1)
+        y = torch.rand((tb,), device="cuda", generator=g, dtype=torch.float32)
+        xt = x[:tb].contiguous()
+        st.train_step(xt, y, None, tb, 1e-4)
+        st.sync()
+        t0 = time.perf_counter()
+        for _ in range(reps * 10):
+            st.train_step(xt, y, None, tb, 1e-4)
+        st.sync()
+        tt = (time.perf_counter() - t0) / (reps * 10)
+        st.free()
+        res["train"].append({"batch": tb, "step_s": tt, "samples_per_s": tb / tt,
+                             "tflops": 3 * fwd * tb / tt / 1e12, "frac_bf16_peak": 3 * fwd * tb / tt / peak})
+    return res
 
 
 def main():
@@ -266,6 +268,9 @@ def main():
                     help="only time the surrogate network: inference on 2^20 rows, training steps")
     ap.add_argument("--sequential", action="store_true",
                     help="only compare the batched slit run with one run per (geometry, species) pair")
+    ap.add_argument("--copy-bandwidth", action="store_true",
+                    help="only time device-to-device copies (torch) from 16 MiB to 4 GiB: the bandwidth a "
+                         "streaming kernel can reach on this GPU, read + write bytes per second")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (known traffic, to scale HBM counters)")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="only summarise rocprofv3 CSV output under DIR")
@@ -299,6 +304,26 @@ def main():
     from paper_1303_2470_amd import inputs, lbmp
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.copy_bandwidth:
+        out = []
+        for mib in (16, 64, 128, 256, 512, 1024, 2048, 4096):
+            n = mib << 20
+            a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            reps = 20 if mib <= 256 else 5
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out.append({"bytes_per_buffer": n, "ms": ms, "read_plus_write_GBs": 2 * n / ms / 1e6})
+            del a, b
+        print(json.dumps({"copy_bandwidth": out}))
+        return
     if args.copy_calibration:
         n = args.copy_calibration << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)

@@ -307,14 +307,72 @@ __global__ void __launch_bounds__(1024) k_bias_grad(const __bf16* __restrict__ d
     }
 }
 
+// Parameter gradients split over the batch (the reduction dimension K = B):
+// wave w takes the 32x32 tile w % tiles of dW = dZ^T A over the rows
+// [split kc, (split + 1) kc), split = w / tiles, and writes its partial to
+// P[split]; block (column group, split) sums the same rows of dZ for the bias
+// gradient into Pb[split]. k_sum_splits adds the partials in split order
+// (deterministic). Spreading K over the waves keeps the whole GPU busy where
+// the 256 x 256 weight gradient has only 64 output tiles.
+constexpr int GSPLIT_MAX = 32;
+
+__global__ void __launch_bounds__(256) k_grad_w_split(const __bf16* __restrict__ dZ, int O,
+                                                      const __bf16* __restrict__ Ap, int I, int kc, int splits,
+                                                      float* __restrict__ P) {
+    const int wave = (blockIdx.x * (blockDim.x / 64)) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    const int tiles_n = I / 32, tiles = (O / 32) * tiles_n;
+    const int split = wave / tiles, t = wave % tiles;
+    if (split >= splits) return;
+    const int m0 = (t / tiles_n) * 32, n0 = (t % tiles_n) * 32;
+    const int r = lane & 31, kh = (lane >> 5) * 8;
+    f32x16 acc = {};
+    for (int k0 = split * kc; k0 < (split + 1) * kc; k0 += 16) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = dZ[(size_t)(k0 + kh + i) * O + m0 + r];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i] = Ap[(size_t)(k0 + kh + i) * I + n0 + r];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    epilogue<EPI_GRAD>(acc, m0, n0, lane, I, nullptr, nullptr, P + (size_t)split * O * I, nullptr);
+}
+
+__global__ void __launch_bounds__(256) k_grad_b_split(const __bf16* __restrict__ dZ, int O, int kc,
+                                                      float* __restrict__ Pb) {
+    __shared__ float part[8][33];
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int n = blockIdx.x * 32 + c, split = blockIdx.y;
+    float s = 0.0f;
+    for (int b = split * kc + g; b < (split + 1) * kc; b += 8) s += (float)dZ[(size_t)b * O + n];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0) {
+        float a = 0.0f;
+        for (int i = 0; i < 8; ++i) a += part[i][c];
+        Pb[(size_t)split * O + n] = a;
+    }
+}
+
+__global__ void k_sum_splits(const float* __restrict__ P, int n, int splits, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float a = 0.0f;
+    for (int sp = 0; sp < splits; ++sp) a += P[(size_t)sp * n + i];
+    out[i] = a;
+}
+
 // Adam on the fp32 master copy (only the unpadded parameters move), then
 // bf16 copies W [out][in] and W^T [in][out].
+// hyper = {lr, c1, c2}: the step's learning rate and bias corrections, read
+// from device memory so that a captured training step can be replayed.
 __global__ void k_adam(float* __restrict__ W, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int rows, int cols, int trows, int tcols,
-                       float lr, float b1, float b2, float eps, float c1, float c2,
+                       const float* __restrict__ hyper, float b1, float b2, float eps,
                        __bf16* __restrict__ Wb, __bf16* __restrict__ WTb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * cols) return;
+    const float lr = hyper[0], c1 = hyper[1], c2 = hyper[2];
     const int r = i / cols, c = i % cols;
     float w = W[i];
     if (r < trows && c < tcols) {
@@ -328,6 +386,12 @@ __global__ void k_adam(float* __restrict__ W, float* __restrict__ m, float* __re
     }
     if (Wb) Wb[i] = (__bf16)w;
     if (WTb) WTb[(size_t)c * rows + r] = (__bf16)w;
+}
+
+__global__ void k_set_hyper(float* __restrict__ hyper, float lr, float c1, float c2) {
+    hyper[0] = lr;
+    hyper[1] = c1;
+    hyper[2] = c2;
 }
 
 __global__ void k_copy_out(const float* __restrict__ Y, int B, float* __restrict__ y) {
@@ -367,6 +431,15 @@ struct lbmp_sg {
     float* yg;           // gathered targets [bmax]
     float* sq;           // per-row squared errors [bmax]
     float* loss;         // [1]
+    float* hyper;        // [4] learning rate and Adam bias corrections of the current step
+    float* gsplit;       // [GSPLIT_MAX][WIDTH][WIDTH] weight-gradient partials over batch splits
+    float* bsplit;       // [GSPLIT_MAX][WIDTH] bias-gradient partials
+    // forward + backward + Adam of one batch size captured as a graph and
+    // replayed (off with LBMP_SG_GRAPH=0, or on the null stream)
+    bool use_graph;
+    int graph_B;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
 };
 
 namespace lbmp {
@@ -395,6 +468,9 @@ static void carve_sg(lbmp_sg* h, Carver& c) {
     carve_n(c, h->yg, B);
     carve_n(c, h->sq, B);
     carve_n(c, h->loss, 4);
+    carve_n(c, h->hyper, 4);
+    carve_n(c, h->gsplit, (size_t)GSPLIT_MAX * WIDTH * WIDTH);
+    carve_n(c, h->bsplit, (size_t)GSPLIT_MAX * WIDTH);
 }
 
 // Inputs normalised and gathered: x[idx[b]] -> (x - mean)/std, t = (y - y_mean)/y_std.
@@ -462,9 +538,17 @@ static void backward(lbmp_sg* h, int B, hipStream_t s) {
     for (int l = NLAYER - 1; l >= 0; --l) {
         const int O = lout(l), I = lin(l);
         const __bf16* Aprev = l == 0 ? h->xb : h->Ab[l - 1];
-        // dW[o][i] = sum_b dZ[b][o] A[b][i]
-        gemm<false, false, EPI_GRAD>(h->dZb[l], O, Aprev, I, O, I, B, nullptr, nullptr, h->L[l].gW, nullptr, s);
-        k_bias_grad<<<(O + 31) / 32, 1024, 0, s>>>(h->dZb[l], B, O, h->L[l].gb);
+        // dW[o][i] = sum_b dZ[b][o] A[b][i], db[o] = sum_b dZ[b][o]: over
+        // batch splits of 256 rows (B a multiple of 32: fewer, longer splits
+        // when B / 256 is small), partials added in split order
+        int splits = 1;
+        while (splits * 2 <= GSPLIT_MAX && B % (splits * 2 * 16) == 0 && B / (splits * 2) >= 256) splits *= 2;
+        const int kc = B / splits;
+        const int waves = (O / 32) * (I / 32) * splits;
+        k_grad_w_split<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(h->dZb[l], O, Aprev, I, kc, splits, h->gsplit);
+        k_sum_splits<<<(unsigned)((O * I + 255) / 256), 256, 0, s>>>(h->gsplit, O * I, splits, h->L[l].gW);
+        k_grad_b_split<<<dim3((unsigned)(O / 32), (unsigned)splits), 256, 0, s>>>(h->dZb[l], O, kc, h->bsplit);
+        k_sum_splits<<<(unsigned)((O + 255) / 256), 256, 0, s>>>(h->bsplit, O, splits, h->L[l].gb);
         if (l > 0) {
             // dA[b][i] = sum_o dZ[b][o] W[o][i]; W^T stored [i][o]
             gemm<true, true, EPI_DACT>(h->dZb[l], O, h->L[l].WTb, O, B, I, O, nullptr, h->Z[l - 1], nullptr,
@@ -473,18 +557,25 @@ static void backward(lbmp_sg* h, int B, hipStream_t s) {
     }
 }
 
-static void adam(lbmp_sg* h, float lr, hipStream_t s) {
-    h->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f - powf(b1, (float)h->step), c2 = 1.0f - powf(b2, (float)h->step);
+constexpr float ADAM_B1 = 0.9f, ADAM_B2 = 0.999f, ADAM_EPS = 1e-8f;
+
+// The Adam update of every layer with the hyper-parameters in h->hyper.
+static void adam(lbmp_sg* h, hipStream_t s) {
     for (int l = 0; l < NLAYER; ++l) {
         Layer& L = h->L[l];
         const int O = lout(l), I = lin(l);
-        k_adam<<<(O * I + 255) / 256, 256, 0, s>>>(L.W, L.mW, L.vW, L.gW, O, I, tout(l), tin(l), lr, b1, b2,
-                                                  eps, c1, c2, L.Wb, L.WTb);
-        k_adam<<<(O + 255) / 256, 256, 0, s>>>(L.b, L.mb, L.vb, L.gb, O, 1, tout(l), 1, lr, b1, b2, eps, c1,
-                                              c2, nullptr, nullptr);
+        k_adam<<<(O * I + 255) / 256, 256, 0, s>>>(L.W, L.mW, L.vW, L.gW, O, I, tout(l), tin(l), h->hyper,
+                                                  ADAM_B1, ADAM_B2, ADAM_EPS, L.Wb, L.WTb);
+        k_adam<<<(O + 255) / 256, 256, 0, s>>>(L.b, L.mb, L.vb, L.gb, O, 1, tout(l), 1, h->hyper, ADAM_B1,
+                                              ADAM_B2, ADAM_EPS, nullptr, nullptr);
     }
+}
+
+// Step counter and the learning rate and bias corrections of this step.
+static void set_hyper(lbmp_sg* h, float lr, hipStream_t s) {
+    h->step += 1;
+    const float c1 = 1.0f - powf(ADAM_B1, (float)h->step), c2 = 1.0f - powf(ADAM_B2, (float)h->step);
+    k_set_hyper<<<1, 1, 0, s>>>(h->hyper, lr, c1, c2);
 }
 
 static lbmp_status check(const lbmp_sg* h) {
@@ -540,6 +631,13 @@ extern "C" lbmp_status sg_create(int batch_max, uint64_t seed, void* dev_ws, siz
     h->bmax = batch_max;
     h->step = 0;
     h->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        const char* e = getenv("LBMP_SG_GRAPH");
+        h->use_graph = h->stream != nullptr && !(e && e[0] == '0');
+    }
+    h->graph_B = 0;
+    h->graph = nullptr;
+    h->gexec = nullptr;
     Carver c(dev_ws, ws_bytes);
     carve_sg(h, c);
     hipStream_t s = h->stream;
@@ -598,7 +696,7 @@ extern "C" lbmp_status sg_set_params(lbmp_sg* h, const float* p) {
         LBMP_HIP(hipMemsetAsync(h->L[l].vb, 0, b.size() * 4, s));
         // bf16 copies through the Adam kernel with lr = 0 and no moving entries
         k_adam<<<(O * I + 255) / 256, 256, 0, s>>>(h->L[l].W, h->L[l].mW, h->L[l].vW, h->L[l].gW, O, I, 0, 0,
-                                                  0.f, 0.f, 0.f, 1.f, 1.f, 1.f, h->L[l].Wb, h->L[l].WTb);
+                                                  h->hyper, 0.f, 0.f, 1.f, h->L[l].Wb, h->L[l].WTb);
         LBMP_HIP(hipStreamSynchronize(s));
     }
     h->step = 0;
@@ -659,9 +757,29 @@ extern "C" lbmp_status sg_train_step(lbmp_sg* h, const float* x_dev, const float
     hipStream_t s = h->stream;
     st = sg_batch_in(h, x_dev, y_dev, idx_dev, B);
     if (st != LBMP_OK) return st;
-    forward(h, B, s);
-    backward(h, B, s);
-    adam(h, lr, s);
+    set_hyper(h, lr, s);
+    if (h->use_graph) {
+        // the step's kernels do not depend on the batch rows or the learning
+        // rate (both in device memory): one graph per batch size
+        if (!h->gexec || h->graph_B != B) {
+            if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+            if (h->graph) (void)hipGraphDestroy(h->graph);
+            h->gexec = nullptr;
+            h->graph = nullptr;
+            LBMP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            forward(h, B, s);
+            backward(h, B, s);
+            adam(h, s);
+            LBMP_HIP(hipStreamEndCapture(s, &h->graph));
+            LBMP_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+            h->graph_B = B;
+        }
+        LBMP_HIP(hipGraphLaunch(h->gexec, s));
+    } else {
+        forward(h, B, s);
+        backward(h, B, s);
+        adam(h, s);
+    }
     LBMP_HIP(hipGetLastError());
     if (loss_host) {
         k_sum<<<1, 256, 0, s>>>(h->sq, B, h->loss);
@@ -728,6 +846,8 @@ extern "C" lbmp_status sg_sync(lbmp_sg* h) {
 extern "C" void sg_free(lbmp_sg* h) {
     if (!h || h->magic != SG_MAGIC) return;
     (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     h->magic = 0;
     delete h;
 }

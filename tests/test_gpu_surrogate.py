@@ -233,3 +233,34 @@ def test_predict_orders_after_current_stream(lb):
     got = (out * 1.0).cpu()          # consumed on the current stream without a sync
     assert torch.equal(got, ref)
     sg.free()
+
+
+def test_training_graph_replays_equal_eager_steps(lb, monkeypatch):
+    """The training step replays a captured graph (forward, backward, Adam);
+    with eager work and synchronisations between replays, a change of batch
+    size (a new capture) and varying learning rates, every step's parameters
+    equal those of the same steps launched one kernel at a time."""
+    import torch
+    rng = np.random.default_rng(7)
+    n = 4096
+    x = torch.tensor(rng.normal(size=(n, 6)), dtype=torch.float32, device="cuda")
+    y = torch.tensor(rng.normal(size=n), dtype=torch.float32, device="cuda")
+    a = lb.Surrogate(1024, seed=11)
+    monkeypatch.setenv("LBMP_SG_GRAPH", "0")
+    b = lb.Surrogate(1024, seed=11)
+    monkeypatch.delenv("LBMP_SG_GRAPH")
+    for sg in (a, b):
+        sg.set_normalization(np.zeros(6), np.ones(6), 0.0, 1.0)
+    assert np.array_equal(a.get_params(), b.get_params())
+    for step, B in enumerate([256, 256, 256, 512, 512, 256]):
+        idx = torch.tensor(rng.permutation(n)[:B].astype(np.int32), device="cuda")
+        lr = 1e-3 * (1 + step) / 3
+        la = a.train_step(x, y, idx, B, lr, want_loss=step % 2 == 0)
+        lb_ = b.train_step(x, y, idx, B, lr, want_loss=step % 2 == 0)
+        assert la == lb_
+        a.predict(x[:64])                           # eager work between replays
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.get_params(), b.get_params()), step
+    a.free()
+    b.free()
