@@ -7,8 +7,12 @@
 //    c_q * rho_ref (mobile) and c_q * Gamma_ref (adsorbed), where rho_ref and
 //    Gamma_ref are the Eq. 11 weights and c_q = 1 for the density and the mean
 //    velocity V_q for the first moments — the long-time limit of each field;
-//  * the receiving node pulls Y = sum_i X(r - c_i) p_i(r - c_i) with an FMA
-//    chain over a receiver-indexed table pin[i][r] = p_i(r - c_i);
+//  * the receiving node pulls Y = sum_i X(r - c_i) p_i(r - c_i) over a
+//    receiver-indexed table pin[i][r] = p_i(r - c_i): an FP64 FMA chain in
+//    the direct, box and z-march kernels; in the LDS-DMA and gathered-chunk
+//    kernels three FP32 FMA chains in link order (links with c_ix = 0, +1,
+//    -1), converted and added in that order (the stochastically rounded
+//    inputs keep their round-to-nearest residuals from repeating);
 //  * X' = ((fma(-X, sigma, X) - p_a X + p_d X_ads) + c_q rho_ref src) + Y
 //    with sigma(r) = sum_i p_i(r) rounded once, and src(r) = sum_i pin_i(r) -
 //    sum_i p_i(r) formed exactly from the stored probabilities (zero wherever
@@ -972,9 +976,18 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
             voff[j] = (e < RREG && G.cls[m] != 0) ? (fidx ? fidx[m] : m) * 4 : OOB;
         }
     }
-    double pin[NL];
+    float pin[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offn);
+    for (int k = 0; k < NL; ++k) pin[k] = bload(tag, mkrsrc(G.pin + (int64_t)k * N, (int64_t)N * 4), offn);
+    if constexpr (FR) {
+        // full rows: a lane forms the arrivals over +x links for the lane at
+        // x + 1 and over -x links for the lane at x - 1, so it holds their
+        // probabilities of those links
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            if (lcx(k) > 0) pin[k] = dpp_f32<DPP_WAVE_ROL1>(pin[k]);
+            else if (lcx(k) < 0) pin[k] = dpp_f32<DPP_WAVE_ROR1>(pin[k]);
+    }
     const double sig = __builtin_bit_cast(
         double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, (int64_t)N * 8), act ? offn * 2 : OOB, 0, 0));
     const double src = (double)bload(tag, mkrsrc(G.src, (int64_t)N * 4), offn);
@@ -1156,37 +1169,44 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     // instruction's immediate (merged pairs need a base register each)
                     using lvf = const volatile __attribute__((address_space(3))) float;
                     lvf* const sb = (lvf*)((const __attribute__((address_space(3))) char*)stg.at<q>() + cbb);
-                    // all 19 values first (the node's own first: the chain starts
-                    // with it), then the arithmetic; v[k] is the value at r - c_k
+                    // all values first, then the arithmetic; v[k] is the value at
+                    // r - c_k (FR: for a link with an x component, the value at
+                    // r - c_k + x-hat * c_kx, the lane's own column of that row)
                     float v[NL], c0;
                     if constexpr (FR) {
-                        // a wave is one periodic row (lane = x): the values at x -+ 1
-                        // are the x-centred values of the same row in the lanes
-                        // beside it (a rotation of the wave by one lane)
                         c0 = sb[SH::at(1, 1, 0)];
     #pragma unroll
                         for (int k = 0; k < NL; ++k)
                             if (lcx(k) == 0) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 0)];
     #pragma unroll
                         for (int k = 0; k < NL; ++k)
-                            if (lcx(k) != 0) {
-                                const float b = row_link(k) < 0 ? c0 : v[row_link(k)];
-                                v[k] = lcx(k) > 0 ? dpp_f32<DPP_WAVE_ROR1>(b) : dpp_f32<DPP_WAVE_ROL1>(b);
-                            }
+                            if (lcx(k) != 0) v[k] = row_link(k) < 0 ? c0 : v[row_link(k)];
                     } else {
                         c0 = sb[SH::at(1, 1, 1)];
     #pragma unroll
                         for (int k = 0; k < NL; ++k) v[k] = sb[SH::at(1 - lcy(k), 1 - lcz(k), 1 - lcx(k))];
                     }
                     const double xc = (double)c0;
-                    double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
-                    acc0 = __builtin_fma(cq[q], src, acc0);
+                    double stay = __builtin_fma(-xc, sig, xc);  // the part that stays (Eq. 7)
+                    stay = __builtin_fma(cq[q], src, stay);
+                    // arrivals from r - c_k (Eq. 7): three FP32 chains in link order,
+                    // over the links with c_kx = 0, +1 and -1
+                    float a0 = 0.0f, ap = 0.0f, am = 0.0f;
     #pragma unroll
-                    for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
-                        if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
-                        else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
+                    for (int k = 0; k < NL; ++k) {
+                        if (lcx(k) == 0) a0 = __builtin_fmaf(v[k], pin[k], a0);
+                        else if (lcx(k) > 0) ap = __builtin_fmaf(v[k], pin[k], ap);
+                        else am = __builtin_fmaf(v[k], pin[k], am);
                     }
-                    double nvx = acc0 + acc1;
+                    if constexpr (FR) {
+                        // a wave is one periodic row (lane = x): the lane formed the
+                        // +x and -x chains of the lanes beside it (pin holds their
+                        // probabilities there), and a rotation of the wave by one
+                        // lane hands each its sum
+                        ap = dpp_f32<DPP_WAVE_ROR1>(ap);
+                        am = dpp_f32<DPP_WAVE_ROL1>(am);
+                    }
+                    double nvx = ((stay + (double)a0) + (double)ap) + (double)am;
                     const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
                     if constexpr (q == 0) red[3] += act ? xc : 0.0;
                     else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
@@ -1313,9 +1333,9 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     int nba[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) nba[k] = act ? 4 * (int)G.gnbr[(int64_t)k * NC + i] : 4 * GZSLOT;
-    double pin[NL];
+    float pin[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) pin[k] = (double)bload(tag, mkrsrc(G.pin + (int64_t)k * G.N, (int64_t)G.N * 4), offn);
+    for (int k = 0; k < NL; ++k) pin[k] = bload(tag, mkrsrc(G.pin + (int64_t)k * G.N, (int64_t)G.N * 4), offn);
     const double sig = __builtin_bit_cast(
         double, __builtin_amdgcn_raw_buffer_load_b64(mkrsrc(G.sig, G.N * 8), act ? offn * 2 : OOB, 0, 0));
     const double src = (double)bload(tag, mkrsrc(G.src, G.N * 4), offn);
@@ -1442,14 +1462,18 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     for (int k = 0; k < NL; ++k)
                         v[k] = *(const volatile __attribute__((address_space(3))) float*)(sb + nba[k]);
                     const double xc = (double)c0;
-                    double acc0 = __builtin_fma(-xc, sig, xc), acc1 = 0.0;  // the part that stays (Eq. 7)
-                    acc0 = __builtin_fma(cq[q], src, acc0);
+                    double stay = __builtin_fma(-xc, sig, xc);  // the part that stays (Eq. 7)
+                    stay = __builtin_fma(cq[q], src, stay);
+                    // arrivals from r - c_k (Eq. 7): the LDS-DMA blocks' three FP32
+                    // chains, over the links with c_kx = 0, +1 and -1
+                    float a0 = 0.0f, ap = 0.0f, am = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < NL; ++k) {  // arrivals from r - c_k (Eq. 7)
-                        if (k & 1) acc1 = __builtin_fma((double)v[k], pin[k], acc1);
-                        else acc0 = __builtin_fma((double)v[k], pin[k], acc0);
+                    for (int k = 0; k < NL; ++k) {
+                        if (lcx(k) == 0) a0 = __builtin_fmaf(v[k], pin[k], a0);
+                        else if (lcx(k) > 0) ap = __builtin_fmaf(v[k], pin[k], ap);
+                        else am = __builtin_fmaf(v[k], pin[k], am);
                     }
-                    double nvx = acc0 + acc1;
+                    double nvx = ((stay + (double)a0) + (double)ap) + (double)am;
                     const uint32_t r = rbase + (uint32_t)f * 0x9e3779b9u;
                     if constexpr (q == 0) red[3] += act ? xc : 0.0;
                     else red[q - 1] = __builtin_fma(xc, w[q - 1], red[q - 1]);
