@@ -72,7 +72,8 @@ struct GeomDev {
     int64_t NC;
     // gathered chunks (variant 8): chunk c covers compact nodes
     // gch[c].x .. gch[c].x + gch[c].y - 1 (one per thread) and the halo
-    // ghsrc[gch[c].z .. + gch[c].w - 1]; node i's lattice index gnode[i], its
+    // quads starting at the compact nodes ghsrc[gch[c].z .. + gch[c].w - 1];
+    // node i's lattice index gnode[i], its
     // adsorbed-field index gaslot[i] (-1 off the interface) and, per link k,
     // the region slot of r - c_k in gnbr[k * NC + i]
     const int4* gch;
@@ -1260,32 +1261,31 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
 // Variant 8: a block updates one chunk of up to GCH fluid nodes that are
 // consecutive in the compact storage, whose order (tiles of 32 x 4 x 4 lattice
 // nodes, fluid nodes in lattice order within a tile) keeps a chunk spatially
-// compact. Per field the buffer unit copies the chunk's own values (one
+// compact. Per field the buffer unit copies, in 16-byte quads (4 consecutive
+// compact values, one quad per thread), the chunk's own values (one
 // contiguous range) and those of its halo (the fluid nodes outside the chunk
-// that its nodes pull from, a precomputed list of compact indices) into an
-// LDS region; each thread then reads its 18 arrivals at precomputed region
-// slots (links from solid nodes read a slot the copy leaves at zero). Every
-// thread has a fluid node, whatever the porosity, and only fluid values are
-// copied. The arithmetic, its order and the rounding bits are those of the
-// LDS-DMA blocks, so the stored fields are bitwise the same.
-// NH = 1 or 2: blocks of 256 or 512 threads (nodes per chunk); the region
-// holds 4 or 3 slots per thread
+// that its nodes pull from, covered by a precomputed list of quad starts)
+// into an LDS region; each thread then reads its 18 arrivals at precomputed
+// region slots (links from solid nodes read a slot the copy leaves at zero).
+// Every thread has a fluid node, whatever the porosity, and only runs of
+// fluid values are copied. The arithmetic, its order and the rounding bits
+// are those of the LDS-DMA blocks, so the stored fields are bitwise the same.
+// NH = 1 or 2: blocks of 256 or 512 threads (nodes per chunk, region quads)
 template <int NH>
 struct GatherShape {
     static constexpr int DBLK = NH * BLK;                 // nodes per chunk, threads per block
-    static constexpr int RLD = NH == 1 ? 4 : 3;           // region copies per thread and field
-    static constexpr int REG = RLD * DBLK;                // region slots: chunk, halo, zeros
-    static constexpr int ZSLOT = REG - 1;                 // never filled: reads 0
+    static constexpr int NQ = DBLK;                       // region quads: one copy per thread and field
+    static constexpr int REG = 4 * NQ;                    // region slots: chunk, halo quads, zeros
+    static constexpr int ZSLOT = REG - 1;                 // in the last quad, never copied: reads 0
 };
 constexpr int GCH = 2 * BLK;                     // the largest chunk
-constexpr int GREG = GatherShape<2>::REG;        // the largest region
 constexpr int GTX = 32, GTY = 4, GTZ = 4;        // ordering tiles (compact storage)
 
 template <int NH>
 __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4))) k_mp_gather(
     const GeomDev<float>* __restrict__ geoms, int ngeom, int gsz, int64_t nblocks, const Ctl* __restrict__ ctl) {
     using GS = GatherShape<NH>;
-    constexpr int DBLK = GS::DBLK, RLD = GS::RLD, NCP = GS::RLD, REGION = GS::REG, STAGE = GS::REG + DBLK;
+    constexpr int DBLK = GS::DBLK, NCP = 1, REGION = GS::REG, STAGE = GS::REG + DBLK;
     constexpr int GZSLOT = GS::ZSLOT;
     constexpr int NW = DBLK / 64;
     constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2, WAIT_IDLE = 2 * NCP;
@@ -1322,13 +1322,10 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const bool anyI = __builtin_amdgcn_ballot_w64(isI) != 0;
     const int offa = isI ? sl * 4 : OOB;
     const int offn = act ? i * 4 : OOB;
-    // region slot e = j * DBLK + tid: chunk node e, halo entry e - C, or nothing
-    int voff[NCP];
-#pragma unroll
-    for (int j = 0; j < NCP; ++j) {
-        const int e = j * DBLK + tid;
-        voff[j] = e < C ? (cbase + e) * 4 : (e < C + H ? G.ghsrc[hoff + e - C] * 4 : OOB);
-    }
+    // region quad tid (slots 4 tid .. 4 tid + 3): chunk nodes 4 tid .. 4 tid + 3,
+    // halo quad tid - Cq, or nothing (H counts the halo quads)
+    const int Cq = (C + 3) >> 2;
+    const int voff = tid < Cq ? (cbase + 4 * tid) * 4 : (tid < Cq + H ? G.ghsrc[hoff + tid - Cq] * 4 : OOB);
     // byte offsets of the 18 arrivals in the region
     int nba[NL];
 #pragma unroll
@@ -1356,29 +1353,19 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     const Stages stg{{st0, st1, st2, st3}};
     const int NB = NC * 4, NIB = NI * 4;
     const int64_t sN = 4 * (int64_t)NC, sNI = 4 * (int64_t)NI;
-    constexpr int GJ = 4096 / (DBLK * 4);
-    int vo[NCP];
-#pragma unroll
-    for (int j = 0; j < NCP; ++j) vo[j] = voff[j] == OOB ? OOB : voff[j] + 4096 - (j % GJ) * DBLK * 4;
-    const int voa = offa == OOB ? OOB : offa + 4096 - (RLD % GJ) * DBLK * 4;
+    const int vo = voff == OOB ? OOB : voff + 4096;
+    const int voa = offa == OOB ? OOB : offa + 4096;
     auto issue = [&](auto qpc, auto anyc, const float* ib, const float* iab) {
         constexpr int qp = decltype(qpc)::value;
-        const auto rin = mkrsrc(reinterpret_cast<const char*>(ib) - 4096, 4 * (int64_t)NB + 4096);
-        float* dst = stg.at<qp>() + wv * 64;
-        auto copy = [&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, LBMP_LDS(dst + (j / GJ) * GJ * DBLK), 4, vo[j], qp * NB,
-                                                     (j % GJ) * DBLK * 4, 0);
-        };
-        static_assert(NCP == 3 || NCP == 4, "three or four region copies per field");
-        copy(std::integral_constant<int, 0>());
-        copy(std::integral_constant<int, 1>());
-        copy(std::integral_constant<int, 2>());
-        if constexpr (NCP == 4) copy(std::integral_constant<int, 3>());
+        // 16 bytes beyond the species' 4 fields: a quad that starts at one of
+        // the last 3 compact nodes reaches past its field (values no slot uses;
+        // the storage continues beyond the last species)
+        const auto rin = mkrsrc(reinterpret_cast<const char*>(ib) - 4096, 4 * (int64_t)NB + 4096 + 16);
+        lds_copy16(rin, stg.at<qp>() + wv * 256, vo, qp * NB);  // wave wv: quads 64 wv .. 64 wv + 63
         if constexpr (decltype(anyc)::value) {
             const auto rina = mkrsrc(reinterpret_cast<const char*>(iab) - 4096, 4 * (int64_t)NIB + 4096);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(dst + (RLD / GJ) * GJ * DBLK), 4, voa,
-                                                     qp * NIB, (RLD % GJ) * DBLK * 4, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rina, LBMP_LDS(stg.at<qp>() + REGION + wv * 64), 4, voa,
+                                                     qp * NIB, 0, 0);
         }
     };
     const int ln = tid & 63;
@@ -2514,12 +2501,14 @@ lbmp_status build_fidx(GeomHost& g, hipStream_t s) {
 // Tables of the gathered-chunk blocks (variant 8) for geometry g. The compact
 // order runs over tiles of GTX x GTY x GTZ lattice nodes and, within a
 // tile, over its fluid nodes in lattice order; chunk c takes compact
-// nodes c GCH .. c GCH + GCH - 1. Its halo lists, sorted, the fluid nodes
-// outside the chunk its nodes pull from (r - c_k), and each node's 18 arrivals
-// get their region slot: the chunk node's own position, GCH.. for the halo in
-// list order, GZSLOT for a solid r - c_k. A chunk whose nodes and halo exceed
-// the region leaves gather_ok false (the tuner then does not offer the
-// variant for the workload).
+// nodes base .. base + C - 1 (C up to the block's threads). Its halo, the
+// fluid nodes outside the chunk its nodes pull from (r - c_k), is covered by
+// quads of 4 consecutive compact nodes, each started at the lowest halo node
+// the quads before it leave out; each node's 18 arrivals get their region
+// slot: the chunk node's own position, 4 (ceil(C / 4) + q) + offset for a
+// halo node in quad q, the zero slot for a solid r - c_k. A chunk whose quads
+// exceed the region even when cut short leaves gather_ok false (the tuner
+// then does not offer the variant for the workload).
 lbmp_status build_gather(GeomHost& g, hipStream_t s) {
     g.gather_ok = false;
     const lbmp_flow* f = g.flow;
@@ -2569,11 +2558,11 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
         }
     g.gnh = 2;
     if (const char* e = getenv("LBMP_GATHER_NH")) g.gnh = atoi(e) == 1 ? 1 : 2;
-    const int64_t CH = (int64_t)g.gnh * BLK;                      // nodes per chunk
+    const int64_t CH = (int64_t)g.gnh * BLK;                      // nodes per chunk, region quads
     const int64_t ZS = g.gnh == 1 ? GatherShape<1>::ZSLOT : GatherShape<2>::ZSLOT;
     const int64_t cap = gather_chunk_cap(NF);
     std::vector<int4> chs;
-    std::vector<int32_t> hsrc, halo, pos(NF, -1);
+    std::vector<int32_t> hsrc, halo, hq, pos(NF, -1);
     std::vector<uint16_t> nbr((size_t)NL * NF);
     auto from = [&](int64_t n, int k) {  // lattice index of r - c_k (periodic)
         const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
@@ -2590,19 +2579,27 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
             }
         std::sort(halo.begin(), halo.end());
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+        hq.clear();
+        for (const int32_t h : halo)
+            if (hq.empty() || h >= hq.back() + 4) hq.push_back(h);
     };
+    // quads the region holds for chunk nodes and halo (the last quad stays zero)
+    auto quads = [&](int64_t C) { return (C + 3) / 4 + (int64_t)hq.size(); };
     for (int64_t base = 0; base < NF;) {
-        // the longest chunk (up to CH nodes, in steps of 64) whose halo fits
+        // the longest chunk (up to CH nodes, in steps of 64) whose quads fit
         int64_t C = std::min<int64_t>(CH, NF - base);
         halo_of(base, C);
-        while (C + (int64_t)halo.size() > ZS && C > 64) {
+        while (quads(C) > CH - 1 && C > 64) {
             C = std::max<int64_t>(64, C - 64);
             halo_of(base, C);
         }
-        const int64_t H = (int64_t)halo.size();
-        if (C + H > ZS || (int64_t)chs.size() >= cap || (int64_t)hsrc.size() + H > cap * GatherShape<1>::REG)
+        const int64_t Cq = (C + 3) / 4, H = (int64_t)hq.size();
+        if (quads(C) > CH - 1 || (int64_t)chs.size() >= cap || (int64_t)hsrc.size() + H > cap * GatherShape<1>::REG)
             return LBMP_OK;  // does not fit the reserved tables: variant not offered
-        for (int64_t e = 0; e < H; ++e) pos[halo[e]] = (int32_t)(C + e);
+        for (size_t e = 0, q = 0; e < halo.size(); ++e) {
+            while (q + 1 < hq.size() && hq[q + 1] <= halo[e]) ++q;
+            pos[halo[e]] = (int32_t)(4 * (Cq + (int64_t)q) + (halo[e] - hq[q]));
+        }
         for (int64_t i = base; i < base + C; ++i)
             for (int k = 0; k < NL; ++k) {
                 const int64_t m = from(gnode[i], k);
@@ -2613,9 +2610,9 @@ lbmp_status build_gather(GeomHost& g, hipStream_t s) {
                 }
                 nbr[(size_t)k * NF + i] = (uint16_t)sl;
             }
-        for (int64_t e = 0; e < H; ++e) pos[halo[e]] = -1;
+        for (const int32_t h : halo) pos[h] = -1;
         chs.push_back(make_int4((int)base, (int)C, (int)hsrc.size(), (int)H));
-        hsrc.insert(hsrc.end(), halo.begin(), halo.end());
+        hsrc.insert(hsrc.end(), hq.begin(), hq.end());
         base += C;
     }
     const int64_t nch = (int64_t)chs.size();
