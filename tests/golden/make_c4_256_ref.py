@@ -13,7 +13,7 @@ converged flow is the 64^3 medium of make_c4_ref.py. The velocity is
 rescaled to the mean fluid velocity Pe D_b / 256; species rates from
 inputs.loguniform_rates(16, 1e-4, 1e-1, seed=2026).
 
-Run: ``OMP_NUM_THREADS=8 python tests/golden/make_c4_256_ref.py`` (about 15
+Run: ``OMP_NUM_THREADS=8 python tests/golden/make_c4_256_ref.py`` (about 20
 minutes on 8 cores, ~10 GB of memory).
 """
 from __future__ import annotations
