@@ -1,6 +1,9 @@
 // Steady fluid flow by the lattice-Boltzmann equation (Eq. 6 of the paper):
 // D3Q19 BGK, Guo forcing, half-way bounce-back, FP64, fused pull-stream +
-// collide, one thread per node, SoA populations [19][N] ping-pong.
+// collide, one thread per fluid node, SoA populations [19][N_F] ping-pong
+// over the fluid nodes only (in lattice order, through a lattice -> compact
+// index map), so that no lane idles on a solid node and no solid value is
+// moved; velocities stay on the dense lattice.
 //
 // The stored state is the post-collision population. A step gathers the
 // post-collision populations of the upstream neighbours (or the reflected
@@ -8,6 +11,7 @@
 // density and the force-corrected velocity u = (sum f c)/rho + g/2, and
 // relaxes towards the equilibrium with the Guo source term.
 #include <mutex>
+#include <vector>
 
 #include "lbmp_internal.hpp"
 
@@ -53,50 +57,54 @@ __device__ inline void bgk_collide(double f[19], const BGKParams& P, double& rho
     }
 }
 
-__global__ void k_bgk_init(const uint8_t* __restrict__ solid, double* __restrict__ fo, int64_t N,
-                           BGKParams P, double* __restrict__ u0) {
+// Start at rest: equilibrium with rho = 1, u = 0, then one collision with the
+// force; the velocity slots of the residual history start at zero on solid
+// nodes (the step kernel writes fluid nodes only).
+__global__ void k_bgk_init(const uint8_t* __restrict__ solid, const int32_t* __restrict__ gidx,
+                           double* __restrict__ fo, int64_t N, int64_t NF, BGKParams P, double* __restrict__ u0,
+                           double* __restrict__ u1, double* __restrict__ u2) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     if (solid[n]) {
-        for (int k = 0; k < 19; ++k) fo[k * N + n] = 0.0;
-        u0[n] = u0[N + n] = u0[2 * N + n] = 0.0;
+        for (int d = 0; d < 3; ++d) u0[d * N + n] = u1[d * N + n] = u2[d * N + n] = 0.0;
         return;
     }
+    const int64_t i = gidx[n];
     double f[19];
     f[0] = W_REST;
 #pragma unroll
     for (int k = 0; k < NL; ++k) f[k + 1] = lw(k);
     double rho, ux, uy, uz;
     bgk_collide(f, P, rho, ux, uy, uz);
-    for (int k = 0; k < 19; ++k) fo[k * N + n] = f[k];
+    for (int k = 0; k < 19; ++k) fo[k * NF + i] = f[k];
     u0[n] = ux;
     u0[N + n] = uy;
     u0[2 * N + n] = uz;
 }
 
-__global__ void k_bgk_step(const uint8_t* __restrict__ solid, const double* __restrict__ fi,
-                           double* __restrict__ fo, int nx, int ny, int nz, BGKParams P,
-                           double* __restrict__ uout) {
+// One step for fluid node i (lattice index gnode[i]): pull from the upstream
+// neighbours through the compact map gidx (-1 on solid nodes: the node's own
+// reflected population instead), collide, store; velocity on the lattice.
+__global__ void k_bgk_step(const int32_t* __restrict__ gnode, const int32_t* __restrict__ gidx,
+                           const double* __restrict__ fi, double* __restrict__ fo, int64_t NF, int nx, int ny,
+                           int nz, BGKParams P, double* __restrict__ uout) {
     const int64_t N = (int64_t)nx * ny * nz;
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    if (solid[n]) {
-        if (uout) uout[n] = uout[N + n] = uout[2 * N + n] = 0.0;
-        return;
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NF) return;
+    const int64_t n = gnode[i];
     const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
     double f[19];
-    f[0] = fi[n];
+    f[0] = fi[i];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         int xs = wrapi(x - lcx(k), nx), ys = wrapi(y - lcy(k), ny), zs = wrapi(z - lcz(k), nz);
-        int64_t src = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-        f[k + 1] = solid[src] ? fi[(int64_t)((k ^ 1) + 1) * N + n] : fi[(int64_t)(k + 1) * N + src];
+        const int32_t j = gidx[xs + (int64_t)nx * (ys + (int64_t)ny * zs)];
+        f[k + 1] = j < 0 ? fi[(int64_t)((k ^ 1) + 1) * NF + i] : fi[(int64_t)(k + 1) * NF + j];
     }
     double rho, ux, uy, uz;
     bgk_collide(f, P, rho, ux, uy, uz);
 #pragma unroll
-    for (int k = 0; k < 19; ++k) fo[(int64_t)k * N + n] = f[k];
+    for (int k = 0; k < 19; ++k) fo[(int64_t)k * NF + i] = f[k];
     if (uout) {
         uout[n] = ux;
         uout[N + n] = uy;
@@ -160,7 +168,7 @@ constexpr int RES_BLOCKS = 512;
 
 static size_t scratch_bytes_for(int64_t N) {
     return 2 * align_up(19 * 8 * (size_t)N) + 3 * align_up(24 * (size_t)N) +
-           align_up(2 * 8 * RES_BLOCKS) + align_up(16);
+           align_up(2 * 8 * RES_BLOCKS) + align_up(16) + 2 * align_up(4 * (size_t)N);
 }
 
 }  // namespace lbmp
@@ -240,9 +248,29 @@ static lbmp_status flow_solve(const lbmp_geometry* g, double tau, const double f
     double* U[3] = {c.take<double>(3 * N), c.take<double>(3 * N), c.take<double>(3 * N)};
     double* part = c.take<double>(2 * RES_BLOCKS);
     double* res = c.take<double>(2);
+    int32_t* gidx = c.take<int32_t>(N);
+    int32_t* gnode = c.take<int32_t>(N);
+    // compact order of the fluid nodes (lattice order) from the host mask
+    const int64_t NF = f->nf;
+    {
+        std::vector<int32_t> gi((size_t)N), gn;
+        gn.reserve((size_t)NF);
+        for (int64_t n = 0; n < N; ++n) {
+            gi[n] = g->solid[n] ? -1 : (int32_t)gn.size();
+            if (!g->solid[n]) gn.push_back((int32_t)n);
+        }
+        if ((int64_t)gn.size() != NF) {
+            delete f;
+            return fail(LBMP_ESTATE, "fluid node count %lld differs from the classification's %lld",
+                        (long long)gn.size(), (long long)NF);
+        }
+        LBMP_HIP(hipMemcpyAsync(gidx, gi.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+        LBMP_HIP(hipMemcpyAsync(gnode, gn.data(), (size_t)NF * 4, hipMemcpyHostToDevice, s));
+        LBMP_HIP(hipStreamSynchronize(s));
+    }
     BGKParams P{tau, force[0], force[1], force[2]};
-    const unsigned nb = (unsigned)((N + 255) / 256);
-    k_bgk_init<<<nb, 256, 0, s>>>(f->d.solid, fa, N, P, U[0]);
+    const unsigned nb = (unsigned)((N + 255) / 256), nbf = (unsigned)((NF + 255) / 256);
+    k_bgk_init<<<nb, 256, 0, s>>>(f->d.solid, gidx, fa, N, NF, P, U[0], U[1], U[2]);
     LBMP_HIP(hipGetLastError());
     double resv = INFINITY;
     int64_t step = 0;
@@ -254,7 +282,7 @@ static lbmp_status flow_solve(const lbmp_geometry* g, double tau, const double f
         // last two steps (the reported velocity)
         const bool need = check || ((sn + 1) % ce) == 0 || ((sn + 2) % ce) == 0 || sn + 1 >= max_steps;
         double* uo = need ? U[sn % 3] : nullptr;
-        k_bgk_step<<<nb, 256, 0, s>>>(f->d.solid, fa, fb, f->nx, f->ny, f->nz, P, uo);
+        k_bgk_step<<<nbf, 256, 0, s>>>(gnode, gidx, fa, fb, NF, f->nx, f->ny, f->nz, P, uo);
         std::swap(fa, fb);
         step = sn;
         if (check) {
@@ -356,9 +384,9 @@ extern "C" lbmp_status lb_flow_solve_static(const lbmp_geometry* g, double tau, 
 }
 
 extern "C" int64_t lb_flow_static_max_nodes(void) {
-    // scratch_bytes_for is 376 bytes per node plus alignment and the residual
+    // scratch_bytes_for is 384 bytes per node plus alignment and the residual
     // partials; the largest N that fits
-    int64_t lo = 0, hi = (int64_t)LBMP_STATIC_SCRATCH_BYTES / 376 + 1;
+    int64_t lo = 0, hi = (int64_t)LBMP_STATIC_SCRATCH_BYTES / 384 + 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) / 2;
         if (scratch_bytes_for(mid) <= (size_t)LBMP_STATIC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
