@@ -176,90 +176,85 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const __bf16* __restrict__ A, 
             epilogue<epi>(acc[i][j], m0 + wm + 32 * i, n0 + wn + 32 * j, lane, N, bias, aux, out0, out1);
 }
 
-// Fused inference: one block (4 waves) per FS samples runs all four layers
-// with the activations in LDS (two buffers, layer l reads one and writes the
-// other) and the weights read as MFMA operands straight from global memory,
-// where all blocks share them in L2. The arithmetic is that of the layer
-// GEMMs (bf16 operands, fp32 accumulation in increasing K, bias and SiLU in
-// fp32, activations rounded to bf16), so predictions equal the unfused path's.
-constexpr int FS = 64;               // samples per block
+// Fused inference: one block (8 waves) per FS samples runs all four layers
+// with the activations in LDS (one buffer: a layer's products read it, and
+// after a barrier its epilogue overwrites it) and the weights read as MFMA
+// operands straight from global memory, where all blocks share them in L2;
+// each weight fragment a wave loads serves the block's 128 samples. The
+// arithmetic is that of the layer GEMMs (bf16 operands, fp32 accumulation in
+// increasing K, bias and SiLU in fp32, activations rounded to bf16), so
+// predictions equal the unfused path's.
+constexpr int FS = 128;              // samples per block
+constexpr int FWAVES = 8;            // waves per block
 constexpr int APITCH = WIDTH + 8;    // bf16 per activation row (padded against bank conflicts)
 
-__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ x, int64_t n,
-                                                     const float* __restrict__ norm,
-                                                     const __bf16* __restrict__ W0, const float* __restrict__ b0,
-                                                     const __bf16* __restrict__ W1, const float* __restrict__ b1,
-                                                     const __bf16* __restrict__ W2, const float* __restrict__ b2,
-                                                     const __bf16* __restrict__ W3, const float* __restrict__ b3,
-                                                     float* __restrict__ y) {
-    __shared__ __align__(16) __bf16 act[2][FS * APITCH];
+__global__ void __launch_bounds__(64 * FWAVES) __attribute__((amdgpu_waves_per_eu(4)))
+k_mlp_forward(const float* __restrict__ x, int64_t n, const float* __restrict__ norm,
+              const __bf16* __restrict__ W0, const float* __restrict__ b0, const __bf16* __restrict__ W1,
+              const float* __restrict__ b1, const __bf16* __restrict__ W2, const float* __restrict__ b2,
+              const __bf16* __restrict__ W3, const float* __restrict__ b3, float* __restrict__ y) {
+    __shared__ __align__(16) __bf16 act[FS * APITCH];
     const int64_t s0 = (int64_t)blockIdx.x * FS;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int r = lane & 31, kh = (lane >> 5) * 8;
     // normalised features, zero padded to PAD_IN columns
-    for (int i = t; i < FS * PAD_IN; i += 256) {
+    for (int i = t; i < FS * PAD_IN; i += 64 * FWAVES) {
         const int row = i / PAD_IN, c = i % PAD_IN;
         const int64_t si = s0 + row;
         float v = 0.0f;
         if (c < NFEAT && si < n) v = (x[si * NFEAT + c] - norm[c]) / norm[6 + c];
-        act[0][row * APITCH + c] = (__bf16)v;
+        act[row * APITCH + c] = (__bf16)v;
     }
     __syncthreads();
-    // hidden layer: wave w computes output features 64 w .. 64 w + 63 of all
+    // hidden layer: wave w computes output features 32 w .. 32 w + 31 of all
     // FS samples as the transposed product (weights as the MFMA's first
     // operand), so each lane holds runs of 4 consecutive features of one
     // sample and writes them to LDS as one 8-byte store
-    auto hidden = [&](const __bf16* __restrict__ W, const float* __restrict__ bias, int K,
-                      const __bf16* in, __bf16* out) {
-        const int n0 = 64 * wave;
-        f32x16 acc[2][2] = {};  // [feature tile][sample tile]
-#pragma unroll 4
+    constexpr int ST = FS / 32;  // sample tiles
+    auto hidden = [&](const __bf16* __restrict__ W, const float* __restrict__ bias, int K) {
+        const int n0 = 32 * wave;
+        f32x16 acc[ST] = {};
+#pragma unroll 2
         for (int k0 = 0; k0 < K; k0 += 16) {
-            bf16x8 w[2], a[2];
+            const bf16x8 w = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + r) * K + k0 + kh);
+            bf16x8 a[ST];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                w[i] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + 32 * i + r) * K + k0 + kh);
-                a[i] = *reinterpret_cast<const bf16x8*>(in + (32 * i + r) * APITCH + k0 + kh);
-            }
+            for (int j = 0; j < ST; ++j) a[j] = *reinterpret_cast<const bf16x8*>(act + (32 * j + r) * APITCH + k0 + kh);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], a[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < ST; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a[j], acc[j], 0, 0, 0);
         }
+        __syncthreads();  // every wave has read the layer's input
         using bf16x4 = __bf16 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int g = 0; g < 4; ++g) {
+            const int nf = n0 + 8 * g + 4 * (lane >> 5);  // features nf .. nf + 3
+            const float4 bc = *reinterpret_cast<const float4*>(bias + nf);
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int nf = n0 + 32 * i + 8 * g + 4 * (lane >> 5);  // features nf .. nf + 3
-                const float4 bc = *reinterpret_cast<const float4*>(bias + nf);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    bf16x4 o;
-                    o[0] = (__bf16)silu(acc[i][j][4 * g + 0] + bc.x);
-                    o[1] = (__bf16)silu(acc[i][j][4 * g + 1] + bc.y);
-                    o[2] = (__bf16)silu(acc[i][j][4 * g + 2] + bc.z);
-                    o[3] = (__bf16)silu(acc[i][j][4 * g + 3] + bc.w);
-                    *reinterpret_cast<bf16x4*>(out + (32 * j + r) * APITCH + nf) = o;
-                }
+            for (int j = 0; j < ST; ++j) {
+                bf16x4 o;
+                o[0] = (__bf16)silu(acc[j][4 * g + 0] + bc.x);
+                o[1] = (__bf16)silu(acc[j][4 * g + 1] + bc.y);
+                o[2] = (__bf16)silu(acc[j][4 * g + 2] + bc.z);
+                o[3] = (__bf16)silu(acc[j][4 * g + 3] + bc.w);
+                *reinterpret_cast<bf16x4*>(act + (32 * j + r) * APITCH + nf) = o;
             }
+        }
     };
-    hidden(W0, b0, PAD_IN, act[0], act[1]);
+    hidden(W0, b0, PAD_IN);
     __syncthreads();
-    hidden(W1, b1, WIDTH, act[1], act[0]);
+    hidden(W1, b1, WIDTH);
     __syncthreads();
-    hidden(W2, b2, WIDTH, act[0], act[1]);
+    hidden(W2, b2, WIDTH);
     __syncthreads();
     // output layer (PAD_OUT features, feature 0 is the network's output), also
-    // transposed: waves 0 and 1 take samples 0-31 and 32-63; feature 0 of
-    // sample 32 w + r sits in element 0 of lane r
-    if (wave < 2) {
+    // transposed: waves 0 .. ST - 1 take samples 32 w .. 32 w + 31; feature 0
+    // of sample 32 w + r sits in element 0 of lane r
+    if (wave < ST) {
         f32x16 acc = {};
 #pragma unroll 4
         for (int k0 = 0; k0 < WIDTH; k0 += 16) {
             const bf16x8 w = *reinterpret_cast<const bf16x8*>(W3 + (size_t)r * WIDTH + k0 + kh);
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(act[1] + (32 * wave + r) * APITCH + k0 + kh);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + (32 * wave + r) * APITCH + k0 + kh);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a, acc, 0, 0, 0);
         }
         const int64_t si = s0 + 32 * wave + r;
@@ -832,7 +827,7 @@ extern "C" lbmp_status sg_predict(lbmp_sg* h, const float* x_dev, int64_t n, flo
     hipStream_t s = h->stream;
     if (n > 0) {
         const Layer* L = h->L;
-        k_mlp_forward<<<(unsigned)((n + FS - 1) / FS), 256, 0, s>>>(x_dev, n, h->norm, L[0].Wb, L[0].b, L[1].Wb,
+        k_mlp_forward<<<(unsigned)((n + FS - 1) / FS), 64 * FWAVES, 0, s>>>(x_dev, n, h->norm, L[0].Wb, L[0].b, L[1].Wb,
                                                                     L[1].b, L[2].Wb, L[2].b, L[3].Wb, L[3].b,
                                                                     y_dev);
     }
