@@ -785,8 +785,10 @@ struct DmaShape {
     __host__ __device__ static constexpr int at(int hy, int pz, int hx) { return (NPL * hy + pz) * RXS + hx; }
     // vector-memory operations a wave issues after a field's copy, up to the
     // wait for it: the copies of the next two fields and the stores of the
-    // two before (with and without interface nodes in the wave)
-    static constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2;
+    // three before (with and without interface nodes in the wave; a field's
+    // copy goes out right after the barrier three fields earlier, before that
+    // field's update and store)
+    static constexpr int WAIT_I = 2 * (NCP + 1) + 3 * 2, WAIT_N = 2 * NCP + 3;
     // waves without a node to update (lane compaction) copy and store nothing else
     static constexpr int WAIT_IDLE = 2 * NCP;
 };
@@ -1152,9 +1154,10 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                 const int f = 4 * s + q;
                 // field f has landed for the whole block once this wave has at
                 // most the operations issued after it outstanding: the loads of
-                // f+1, f+2 and the stores of f-2, f-1 (2 (NCP + 1) + 2 * 2 with
-                // interface nodes in the wave, 2 NCP + 2 without)
-                if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
+                // f+1, f+2 and the stores of f-3, f-2, f-1 (2 (NCP + 1) + 3 * 2
+                // with interface nodes in the wave, 2 NCP + 3 without); the
+                // block's first three and last two fields have fewer behind them
+                if constexpr ((FIRST && q < 3) || (LAST && q >= 2)) barrier_vm0();
                 else if constexpr (IDLE) barrier_vm<SH::WAIT_IDLE>();
                 else if constexpr (ANYI) barrier_vm<SH::WAIT_I>();
                 else barrier_vm<SH::WAIT_N>();
@@ -1167,6 +1170,11 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     pend2 = pend;
                     pend = -1;
                 }
+                // field f + 3 (quantity 3 of this species, or quantity q - 1 of the
+                // next) into the stage of field f - 1, which every wave has read
+                // before this barrier
+                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
+                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
                 if constexpr (!IDLE) {  // an idle wave updates no node
                     // one live base offset: addresses derived from it are not
                     // hoisted out of the loop (each would hold a register for the
@@ -1228,9 +1236,6 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     }
                     bstore_nt(sround(nvx, r), rout, offn, q * NB);
                 }
-                // field f + 3: quantity 3 of this species, or quantity q - 1 of the next
-                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
-                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
             };
             field(std::integral_constant<int, 0>());
             field(std::integral_constant<int, 1>());
@@ -1295,7 +1300,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
     constexpr int DBLK = GS::DBLK, NCP = 1, REGION = GS::REG, STAGE = GS::REG + DBLK;
     constexpr int GZSLOT = GS::ZSLOT;
     constexpr int NW = DBLK / 64;
-    constexpr int WAIT_I = 2 * (NCP + 1) + 2 * 2, WAIT_N = 2 * NCP + 2, WAIT_IDLE = 2 * NCP;
+    constexpr int WAIT_I = 2 * (NCP + 1) + 3 * 2, WAIT_N = 2 * NCP + 3, WAIT_IDLE = 2 * NCP;
     __shared__ __align__(16) float st0[STAGE];
     __shared__ __align__(16) float st1[STAGE];
     __shared__ __align__(16) float st2[STAGE];
@@ -1434,7 +1439,7 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
             auto field = [&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 const int f = 4 * s + q;
-                if constexpr ((FIRST && q < 2) || (LAST && q >= 2)) barrier_vm0();
+                if constexpr ((FIRST && q < 3) || (LAST && q >= 2)) barrier_vm0();
                 else if constexpr (IDLE) barrier_vm<WAIT_IDLE>();
                 else if constexpr (ANYI) barrier_vm<WAIT_I>();
                 else barrier_vm<WAIT_N>();
@@ -1447,6 +1452,11 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     pend2 = pend;
                     pend = -1;
                 }
+                // field f + 3 (quantity 3 of this species, or quantity q - 1 of the
+                // next) into the stage of field f - 1, which every wave has read
+                // before this barrier
+                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
+                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
                 if constexpr (!IDLE) {
                     using lvc = const volatile __attribute__((address_space(3))) char;
                     lvc* const sb = (lvc*)stg.at<q>();
@@ -1481,8 +1491,6 @@ __global__ void __launch_bounds__(NH * BLK) __attribute__((amdgpu_waves_per_eu(4
                     }
                     bstore(sround(nvx, r), rout, offn, q * NB);
                 }
-                if constexpr (q == 0) issue(std::integral_constant<int, 3>(), anyc, in_s, ina_s);
-                else if constexpr (!LAST) issue(std::integral_constant<int, q - 1>(), anyc, in_n, ina_n);
             };
             field(std::integral_constant<int, 0>());
             field(std::integral_constant<int, 1>());
