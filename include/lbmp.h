@@ -268,6 +268,28 @@ lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, double* Xads)
  * wall time of the whole sequence, in milliseconds. For measurement.
  */
 lbmp_status mp_profile_steps(lbmp_mp* h, int64_t n_steps, double* ms_step_kernel, double* ms_total);
+/*
+ * Checkpoint and resume. A checkpoint is a host byte buffer holding the state
+ * after the last step: the stored fields of every (geometry, species) in the
+ * handle's storage precision (fluid nodes in lattice order, adsorbed values in
+ * interface-list order, so it does not depend on the step kernel the tuner
+ * chose), the recorded per-step sums and the watchdog's state, behind a
+ * header with a fingerprint of the set-up (shapes, node counts, rates, Eq. 11
+ * references, mean velocities, Z(0)).
+ * mp_checkpoint_bytes: the size a checkpoint of h takes now.
+ * mp_save: synchronises the stream and writes the checkpoint into host_buf
+ *   (caller-owned, at least mp_checkpoint_bytes); LBMP_EINVAL if it is NULL or
+ *   too small.
+ * mp_load: restores a checkpoint into h, which must have been created for the
+ *   same workload (same flows, species, precision and mode; LBMP_EINVAL
+ *   otherwise, or for a buffer that is not a whole checkpoint) with
+ *   max_steps_recorded at least the checkpoint's step (LBMP_ESTATE). Steps run
+ *   after it give, with the same step kernel, the same bits as steps run
+ *   without interruption.
+ */
+lbmp_status mp_checkpoint_bytes(const lbmp_mp* h, size_t* bytes);
+lbmp_status mp_save(lbmp_mp* h, void* host_buf, size_t bytes);
+lbmp_status mp_load(lbmp_mp* h, const void* host_buf, size_t bytes);
 /* Synchronises the handle's stream and releases the handle. */
 void mp_free(lbmp_mp* h);
 

@@ -3038,6 +3038,168 @@ extern "C" lbmp_status mp_state(lbmp_mp* h, int geom, int species, double* X, do
     return LBMP_OK;
 }
 
+// ---------------------------------------------------------------- checkpoint
+// A checkpoint holds the state at the last step: for every geometry the
+// stored (deviation) fields of every species in the storage precision, fluid
+// nodes in lattice order, the adsorbed fields in interface-list order, the
+// recorded per-step sums, and the watchdog's state; a fingerprint of the
+// set-up (shapes, node counts, rates, Eq. 11 references, mean velocities,
+// Z(0)) guards against loading it into a handle of another workload. The
+// canonical order does not depend on the step kernel the tuner chose.
+namespace lbmp {
+namespace {
+
+constexpr uint64_t CKP_MAGIC = 0x31504B43504D424CULL;  // "LBMPCKP1" little-endian
+struct CkpHeader {
+    uint64_t magic, fingerprint, payload;
+    int64_t steps, bad_t;
+    int32_t prec, ngeom, uptake, pad;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+uint64_t ckp_fingerprint(const lbmp_mp* h) {
+    uint64_t f = 1469598103934665603ULL;
+    const int32_t head[3] = {h->prec, h->ngeom, h->uptake};
+    f = fnv1a(f, head, sizeof head);
+    for (const auto& g : h->g) {
+        const int64_t dims[7] = {g.flow->nx, g.flow->ny, g.flow->nz, g.N, g.NI, g.nf, g.S};
+        f = fnv1a(f, dims, sizeof dims);
+        f = fnv1a(f, &g.lam, sizeof g.lam);
+        for (const auto* v : {&g.pa, &g.pd, &g.rho_ref, &g.gam_ref, &g.V, &g.Z0, &g.bmu})
+            f = fnv1a(f, v->data(), v->size() * sizeof(double));
+    }
+    return f;
+}
+
+size_t ckp_payload(const lbmp_mp* h, int64_t steps) {
+    const size_t es = h->prec == LBMP_FP32 ? 4 : 8;
+    size_t b = 0;
+    for (const auto& g : h->g)
+        b += (size_t)g.S * 4 * ((size_t)g.nf + (size_t)g.NI) * es + (size_t)steps * g.S * NRED * 8;
+    return b;
+}
+
+// device position of the field value of lattice node n (-1 on solid nodes)
+// and of interface slot i's adsorbed value
+struct CkpMaps {
+    std::vector<int64_t> node;  // fluid nodes in lattice order -> device index
+    std::vector<int64_t> slot;  // interface slots -> device index
+};
+lbmp_status ckp_maps(const lbmp_mp* h, const GeomHost& g, CkpMaps& m) {
+    std::vector<int8_t> cls(g.N);
+    LBMP_HIP(hipMemcpyAsync(cls.data(), g.flow->d.cls, g.N, hipMemcpyDeviceToHost, h->stream));
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    const std::vector<int32_t>* map = !compact_fields(h) ? nullptr : (h->variant == 8 ? &g.gidx_h : &g.fidx_h);
+    m.node.clear();
+    m.node.reserve(g.nf);
+    for (int64_t n = 0; n < g.N; ++n)
+        if (cls[n]) m.node.push_back(map ? (int64_t)(*map)[n] : n);
+    if ((int64_t)m.node.size() != g.nf) return fail(LBMP_ESTATE, "fluid node count differs from the set-up");
+    m.slot.resize(g.NI);
+    for (int64_t i = 0; i < g.NI; ++i) m.slot[i] = h->variant == 8 ? g.aperm_h[i] : i;
+    return LBMP_OK;
+}
+
+}  // namespace
+}  // namespace lbmp
+
+extern "C" lbmp_status mp_checkpoint_bytes(const lbmp_mp* h, size_t* bytes) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (!bytes) return fail(LBMP_EINVAL, "bytes is NULL");
+    *bytes = sizeof(CkpHeader) + ckp_payload(h, h->steps);
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_save(lbmp_mp* h, void* host_buf, size_t bytes) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    const size_t need = sizeof(CkpHeader) + ckp_payload(h, h->steps);
+    if (!host_buf || bytes < need) return fail(LBMP_EINVAL, "checkpoint buffer of %zu bytes, need %zu", bytes, need);
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    Ctl c;
+    LBMP_HIP(hipMemcpy(&c, h->ctl, sizeof c, hipMemcpyDeviceToHost));
+    CkpHeader hd{CKP_MAGIC, ckp_fingerprint(h), need - sizeof(CkpHeader), h->steps, c.bad_t, h->prec, h->ngeom,
+                 h->uptake, 0};
+    char* out = static_cast<char*>(host_buf);
+    memcpy(out, &hd, sizeof hd);
+    out += sizeof hd;
+    const size_t es = h->prec == LBMP_FP32 ? 4 : 8;
+    const int64_t t = h->steps + 1;  // the current state's time: its fields are in X1 when t is odd
+    for (auto& g : h->g) {
+        CkpMaps m;
+        st = ckp_maps(h, g, m);
+        if (st != LBMP_OK) return st;
+        const int64_t NC = compact_fields(h) ? g.nf : g.N, NIa = std::max<int64_t>(g.NI, 1);
+        std::vector<char> hx((size_t)g.S * 4 * NC * es), ha((size_t)g.S * 4 * NIa * es);
+        LBMP_HIP(hipMemcpyAsync(hx.data(), (t & 1) ? g.X1 : g.X0, hx.size(), hipMemcpyDeviceToHost, h->stream));
+        LBMP_HIP(hipMemcpyAsync(ha.data(), g.Xa, ha.size(), hipMemcpyDeviceToHost, h->stream));
+        LBMP_HIP(hipStreamSynchronize(h->stream));
+        for (int64_t f = 0; f < (int64_t)g.S * 4; ++f)
+            for (int64_t k = 0; k < g.nf; ++k, out += es) memcpy(out, hx.data() + (f * NC + m.node[k]) * es, es);
+        for (int64_t f = 0; f < (int64_t)g.S * 4; ++f)
+            for (int64_t i = 0; i < g.NI; ++i, out += es) memcpy(out, ha.data() + (f * NIa + m.slot[i]) * es, es);
+        const size_t sb = (size_t)h->steps * g.S * NRED * 8;
+        if (sb) LBMP_HIP(hipMemcpy(out, g.series, sb, hipMemcpyDeviceToHost));
+        out += sb;
+    }
+    return LBMP_OK;
+}
+
+extern "C" lbmp_status mp_load(lbmp_mp* h, const void* host_buf, size_t bytes) {
+    lbmp_status st = check_mp(h);
+    if (st != LBMP_OK) return st;
+    if (!host_buf || bytes < sizeof(CkpHeader)) return fail(LBMP_EINVAL, "checkpoint buffer too small");
+    CkpHeader hd;
+    memcpy(&hd, host_buf, sizeof hd);
+    if (hd.magic != CKP_MAGIC) return fail(LBMP_EINVAL, "not a moment-propagation checkpoint");
+    if (hd.prec != h->prec || hd.ngeom != h->ngeom || hd.uptake != h->uptake || hd.fingerprint != ckp_fingerprint(h))
+        return fail(LBMP_EINVAL, "checkpoint of another workload (geometries, species, precision or mode differ)");
+    if (hd.steps < 0 || hd.steps > h->tmax)
+        return fail(LBMP_ESTATE, "checkpoint at step %lld beyond max_steps_recorded = %lld", (long long)hd.steps,
+                    (long long)h->tmax);
+    const size_t payload = ckp_payload(h, hd.steps);
+    if (hd.payload != payload || bytes < sizeof hd + payload)
+        return fail(LBMP_EINVAL, "checkpoint buffer of %zu bytes, need %zu", bytes, sizeof hd + payload);
+    LBMP_HIP(hipStreamSynchronize(h->stream));
+    const char* in = static_cast<const char*>(host_buf) + sizeof hd;
+    const size_t es = h->prec == LBMP_FP32 ? 4 : 8;
+    const int64_t t = hd.steps + 1;
+    for (auto& g : h->g) {
+        CkpMaps m;
+        st = ckp_maps(h, g, m);
+        if (st != LBMP_OK) return st;
+        const int64_t NC = compact_fields(h) ? g.nf : g.N, NIa = std::max<int64_t>(g.NI, 1);
+        // solid nodes (dense fields) and unused slots stay zero
+        std::vector<char> hx((size_t)g.S * 4 * NC * es, 0), ha((size_t)g.S * 4 * NIa * es, 0);
+        for (int64_t f = 0; f < (int64_t)g.S * 4; ++f)
+            for (int64_t k = 0; k < g.nf; ++k, in += es) memcpy(hx.data() + (f * NC + m.node[k]) * es, in, es);
+        for (int64_t f = 0; f < (int64_t)g.S * 4; ++f)
+            for (int64_t i = 0; i < g.NI; ++i, in += es) memcpy(ha.data() + (f * NIa + m.slot[i]) * es, in, es);
+        LBMP_HIP(hipMemcpy((t & 1) ? g.X1 : g.X0, hx.data(), hx.size(), hipMemcpyHostToDevice));
+        LBMP_HIP(hipMemcpy(g.Xa, ha.data(), ha.size(), hipMemcpyHostToDevice));
+        const size_t sb = (size_t)hd.steps * g.S * NRED * 8;
+        if (sb) LBMP_HIP(hipMemcpy(g.series, in, sb, hipMemcpyHostToDevice));
+        in += sb;
+    }
+    Ctl c;
+    LBMP_HIP(hipMemcpy(&c, h->ctl, sizeof c, hipMemcpyDeviceToHost));
+    c.t = t;
+    c.done = 0;
+    c.bad_t = hd.bad_t;
+    LBMP_HIP(hipMemcpy(h->ctl, &c, sizeof c, hipMemcpyHostToDevice));
+    h->steps = hd.steps;
+    return LBMP_OK;
+}
+
 extern "C" lbmp_status mp_profile_steps(lbmp_mp* h, int64_t n_steps, double* ms_step_kernel,
                                         double* ms_total) {
     lbmp_status st = check_mp(h);

@@ -51,7 +51,8 @@ EXPORTS = ["lbmp_last_error", "lbmp_version", "lb_flow_workspace_bytes", "lb_flo
            "lb_flow_solve_static", "lb_flow_static_max_nodes", "lb_flow_from_velocity", "lb_flow_velocity", "lb_flow_classes", "lb_flow_free",
            "mp_workspace_bytes", "mp_init", "mp_init_charged", "mp_step_n", "mp_vacf", "mp_steps_done", "mp_stats",
            "mp_uptake_init", "mp_uptake",
-           "mp_state", "mp_profile_steps", "mp_free", "sg_param_count", "sg_workspace_bytes",
+           "mp_state", "mp_profile_steps", "mp_checkpoint_bytes", "mp_save", "mp_load", "mp_free",
+           "sg_param_count", "sg_workspace_bytes",
            "sg_create", "sg_set_params", "sg_get_params", "sg_set_normalization", "sg_train_step",
            "sg_gradients", "sg_predict", "sg_sync", "sg_free"]
 
@@ -99,6 +100,9 @@ def load_library(path: str = LIB_PATH):
         "mp_stats": ([vp, i32, P(Stats)], i32),
         "mp_state": ([vp, i32, i32, vp, vp], i32),
         "mp_profile_steps": ([vp, i64, P(dbl), P(dbl)], i32),
+        "mp_checkpoint_bytes": ([vp, P(ctypes.c_size_t)], i32),
+        "mp_save": ([vp, vp, ctypes.c_size_t], i32),
+        "mp_load": ([vp, vp, ctypes.c_size_t], i32),
         "mp_free": ([vp], None),
         "sg_param_count": ([P(i64)], i32),
         "sg_workspace_bytes": ([i32, P(sz)], i32),
@@ -426,6 +430,21 @@ def mp_state(mp: MP, geom: int, species: int):
     Xa = np.zeros((4,) + shape)
     _check(_lib.mp_state(mp.handle, geom, species, _ptr(X), _ptr(Xa)))
     return X, Xa
+
+
+def mp_save(mp: MP) -> np.ndarray:
+    """Checkpoint of the handle's current state (host bytes; see mp_load)."""
+    n = ctypes.c_size_t()
+    _check(_lib.mp_checkpoint_bytes(mp.handle, ctypes.byref(n)))
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(_lib.mp_save(mp.handle, _ptr(buf), buf.nbytes))
+    return buf
+
+
+def mp_load(mp: MP, buf) -> None:
+    """Restores a checkpoint written by mp_save into a handle of the same workload."""
+    b = np.ascontiguousarray(np.frombuffer(buf, dtype=np.uint8) if not isinstance(buf, np.ndarray) else buf)
+    _check(_lib.mp_load(mp.handle, _ptr(b), b.nbytes))
 
 
 def version() -> str:
