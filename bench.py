@@ -70,8 +70,36 @@ def build_porous(lb):
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "mp_step_traffic.json")
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without its comments and blank lines (string and character
+    literals kept as they are), each line stripped of surrounding spaces."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":                                   # literal: copy up to its closing quote
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            while i < n and src[i] != "\n":
+                i += 1
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (l.strip() for l in "".join(out).splitlines())
+    return "\n".join(l for l in lines if l)
+
+
 def kernel_source_sha() -> str:
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip"), "rb").read()).hexdigest()
+    """Hash of the propagation kernels' code (comments and layout ignored), the
+    key under which measured traffic is recorded."""
+    src = open(os.path.join(ROOT, "paper_1303_2470_amd", "csrc", "mp.hip"), encoding="utf-8").read()
+    return hashlib.sha256(strip_comments(src).encode()).hexdigest()
 
 
 def traffic_record(key: str):
@@ -287,7 +315,9 @@ def main():
         ent = traffic_from_counters(args.traffic_record, 1024 << 20)
         rec = json.load(open(TRAFFIC_PATH)) if os.path.exists(TRAFFIC_PATH) else {}
         if rec.get("kernel_source_sha256") != kernel_source_sha():
-            rec = {"kernel": "k_mp_dma", "kernel_source_sha256": kernel_source_sha(), "tiles": {}}
+            rec = {"kernel": "k_mp_dma", "kernel_source_sha256": kernel_source_sha(),
+                   "key": "sha256 of paper_1303_2470_amd/csrc/mp.hip with comments and blank lines removed",
+                   "tiles": {}}
         ent["workload"] = args.workload
         rec["tiles"][f'{args.workload}:{ent["tile"]}'] = ent
         with open(TRAFFIC_PATH, "w") as fh:

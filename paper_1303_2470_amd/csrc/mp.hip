@@ -1853,7 +1853,7 @@ struct GeomHost {
     int32_t* fidx;  // [N] index of a fluid node among the fluid nodes in lattice order, -1 on solid
     std::vector<int32_t> fidx_h;  // host copy
     // gathered chunks (variant 8): the compact order of their fields (gidx,
-    // tiles of 8^3 nodes), chunk table, halo lists, neighbour slots, lattice
+    // tiles of 32 x 4 x 4 nodes), chunk table, halo quads, neighbour slots, lattice
     // index and adsorbed-field index per compact node, adsorbed-field index
     // per interface slot (aperm); host copies of gidx and aperm
     int32_t *gidx, *gnode, *gaslot, *ghsrc, *aperm;
@@ -1880,7 +1880,7 @@ struct lbmp_mp {
     double* chunk;   // [nwork][nch_max][NRED] chunk sums of the series reduction
     int nch_max, nch;
     double* setup_tmp;
-    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3-7: LDS DMA (FP32)
+    int K, gsz, variant;  // variant 0: direct loads, 1: LDS-staged box, 2: z-march, 3-7: LDS DMA, 8: gathered chunks (FP32)
     int uptake;           // out-of-equilibrium density propagation (no VACF)
     int64_t nblocks;
     hipGraph_t graph = nullptr;

@@ -28,3 +28,17 @@ def test_more_than_one_gpu_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_key_ignores_comments_only():
+    """The traffic record's key: a comment or blank-line edit keeps it, a code
+    edit changes it; literals that look like comments are code."""
+    import hashlib
+    import bench
+    a = 'int f() { return 1; } // one\nconst char* s = "a//b /* c */";\n'
+    b = '/* header */\n  int f() { return 1; }\n\n  const char* s = "a//b /* c */"; // two\n'
+    c = 'int f() { return 2; }\nconst char* s = "a//b /* c */";\n'
+    h = lambda s: hashlib.sha256(bench.strip_comments(s).encode()).hexdigest()
+    assert bench.strip_comments(a) == 'int f() { return 1; }\nconst char* s = "a//b /* c */";'
+    assert h(a) != h(c)
+    assert h(b) == h(a)
